@@ -1,0 +1,165 @@
+"""Pins of the reference evaluator against facts fixed by the paper and by mathematics.
+
+Each test targets a plausible mistake in the oracle: a wrong singular
+substitution (closed forms at small r), a dropped 1/2pi or sign (closed forms),
+a causality leak, a window that does not partition unity, a mis-sized panel for
+oscillatory signatures (independent QUADPACK integration), and the blending
+function (its closed-form Fourier transform from Sec. 2.1).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from wfp_workloads import FAMILY_E, FAMILY_G, FAMILY_RAMP, FAMILY_STEP, config
+
+
+def one(fam, A=1.0, t0=0.0, w=0.0, s=0.0):
+    return dict(family=[fam], amp=[A], t0=[t0], omega=[w], s=[s])
+
+
+def u1(src, tgt, t, sig, **kw):
+    return oracle.u_direct(np.array([src]), sig["family"], sig["amp"], sig["t0"], sig["omega"], sig["s"],
+                           np.array([tgt]), [t], **kw)[0]
+
+
+@pytest.mark.parametrize("r,t", [(0.3, 1.0), (1e-6, 0.5), (1e-9, 3.0), (1.2, 5.0), (2.5, 2.6), (0.5, 0.7)])
+def test_step_signature_closed_form(r, t):
+    # sigma = H(t): u = (1/2pi) acosh(t/r) for t > r  (from eqs. solnRep and Green)
+    src = (0.125, -0.25)
+    tgt = (src[0] + r, src[1])
+    rr = math.hypot(tgt[0] - src[0], tgt[1] - src[1])
+    u = u1(src, tgt, t, one(FAMILY_STEP))
+    assert u == pytest.approx(math.acosh(t / rr) / (2 * math.pi), rel=1e-13)
+
+
+def _ramp_closed(r, t):
+    # (1/2pi)[t acosh(t/r) - sqrt(t^2-r^2)] = (r/2pi)(V cosh V - sinh V), t = r cosh V
+    V = math.acosh(t / r)
+    if V < 1e-2:
+        g = sum(V ** (2 * k + 1) * (1.0 / math.factorial(2 * k) - 1.0 / math.factorial(2 * k + 1))
+                for k in range(1, 8))
+    else:
+        g = V * math.cosh(V) - math.sinh(V)
+    return r * g / (2 * math.pi)
+
+
+@pytest.mark.parametrize("r,t", [(0.3, 1.0), (1e-5, 0.5), (0.5, 0.50001), (1.0, 4.0)])
+def test_ramp_signature_closed_form(r, t):
+    src = (-0.5, 0.25)
+    tgt = (src[0], src[1] + r)
+    rr = abs(tgt[1] - src[1])
+    u = u1(src, tgt, t, one(FAMILY_RAMP))
+    assert u == pytest.approx(_ramp_closed(rr, t), rel=1e-12)
+
+
+def test_causality_and_onset():
+    # G = 0 outside the light cone (eq. Green); sigma = 0 before its onset
+    sig = one(FAMILY_G, A=1.3, t0=0.4, w=4 * math.pi, s=0.25)
+    r = 0.7
+    for t in [0.05, 0.5, 1.0, 1.0999]:       # t - r < t0
+        assert u1((0, 0), (r, 0), t, sig) == 0.0
+    assert abs(u1((0, 0), (r, 0), 1.6, sig)) > 0.0
+
+
+def test_linearity_and_radial_symmetry():
+    rng = np.random.default_rng(3)
+    src = np.array([[0.1, 0.2], [0.1, 0.2]])
+    fam = [FAMILY_E, FAMILY_E]
+    th = rng.uniform(0, 2 * np.pi, 6)
+    tg = np.stack([0.1 + 0.37 * np.cos(th), 0.2 + 0.37 * np.sin(th)], 1)
+    ua = oracle.u_direct(src, fam, [0.7, -1.9], [0.3, 0.3], [20.0, 20.0], [0, 0], tg, 2.0)
+    ub = oracle.u_direct(src[:1], fam[:1], [0.7 - 1.9], [0.3], [20.0], [0], tg, 2.0)
+    np.testing.assert_allclose(ua, ub, rtol=1e-13)
+    np.testing.assert_allclose(ub, ub[0], rtol=1e-13)   # radial symmetry of G
+
+
+@pytest.mark.parametrize("fam,w,s,t0,r,t", [
+    (FAMILY_E, 31.4, 0.0, 0.6, 0.21, 2.3),
+    (FAMILY_E, 94.2, 0.0, 0.2, 0.05, 1.7),
+    (FAMILY_G, 4 * math.pi, 0.25, 0.3, 0.4, 3.1),
+    (FAMILY_G, 20 * math.pi, 0.05, 0.1, 0.013, 0.9),
+])
+def test_against_quadpack(fam, w, s, t0, r, t):
+    # independent integration: QUADPACK's algebraic-weight rule handles (tau - r)^(-1/2)
+    sig = one(fam, A=1.0, t0=t0, w=w, s=s)
+    from wfp_workloads import sigma_np
+    f = lambda tau: sigma_np(np.array([fam]), np.array([1.0]), np.array([t0]), np.array([w]),
+                             np.array([s]), t - tau)[0] / math.sqrt(tau + r)
+    val, err = integrate.quad(f, r, t, weight="alg", wvar=(-0.5, 0.0), limit=5000, epsabs=1e-15,
+                              epsrel=1e-13)
+    u = u1((0.0, 0.0), (r, 0.0), t, sig)
+    assert u == pytest.approx(val / (2 * math.pi), rel=2e-11, abs=1e-15)
+
+
+def test_refinement_invariance_config0():
+    w = config(0)
+    ti = np.arange(0, 64, 9)
+    ts = w.dt * np.array([37, 80, 150, 200])
+    a = oracle.u_workload(w, ti, ts)
+    b = oracle.u_workload(w, ti, ts, npp=24, hscale=0.5)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+
+
+def _kb_ft_closed(om, delta, b):
+    # Sec. 2.1: FT of phi' = b/sinh(b) sinc(sqrt((delta om/2)^2 - b^2)) times a phase.  The
+    # paper prints e^{-i delta om/2}; with its stated kernel e^{+i om t} (same section) and
+    # phi' supported on [0, delta] and symmetric about delta/2 the phase is e^{+i delta om/2},
+    # which is the reading pinned here.
+    z2 = (delta * om / 2) ** 2 - b * b
+    if z2 >= 0:
+        z = math.sqrt(z2)
+        sinc = math.sin(z) / z if z > 0 else 1.0
+    else:
+        z = math.sqrt(-z2)
+        sinc = math.sinh(z) / z
+    return b * np.exp(+1j * delta * om / 2) / math.sinh(b) * sinc
+
+
+@pytest.mark.parametrize("delta,b", [(1.2, math.log(1e7)), (0.0179, math.log(1e7)), (1.0, 30.0)])
+def test_blending_function_fourier_closed_form(delta, b):
+    x, wq = np.polynomial.legendre.leggauss(200)
+    t = 0.5 * delta * (x + 1)
+    _, dphi = oracle.phi(t, delta, b)
+    for om in [0.0, 3.0 / delta, 20.0 / delta, 2 * b / delta, 60.0 / delta]:
+        ft = 0.5 * delta * np.sum(wq * dphi * np.exp(1j * om * t))
+        ref = _kb_ft_closed(om, delta, b)
+        assert abs(ft - ref) <= 1e-12 * max(1.0, abs(ref))
+    p, _ = oracle.phi(np.array([0.0, 0.5 * delta, delta, 2 * delta]), delta, b)
+    np.testing.assert_allclose(p, [0.0, 0.5, 1.0, 1.0], atol=1e-14)   # symmetry of the bump
+
+
+def test_windows_partition_unity():
+    # eq. split: u_l + u_nh + u_fh = u for targets in B (r > 0), for any blending parameters
+    w = config(0)
+    delta, b, Ap = 1.2, math.log(1e7), 6.0
+    ti = np.array([0, 5, 33])
+    ts = np.array([2.0, 6.2, 9.7])
+    kw = dict(delta=delta, b=b, Aplus=Ap)
+    full = oracle.u_workload(w, ti, ts, **kw)
+    parts = sum(oracle.u_workload(w, ti, ts, window=k, **kw) for k in (1, 2, 3))
+    np.testing.assert_allclose(parts, full, rtol=1e-12, atol=1e-14 * np.abs(full).max())
+    hist = oracle.u_workload(w, ti, ts, window=oracle.WIN_HISTORY, **kw)
+    loc = oracle.u_workload(w, ti, ts, window=oracle.WIN_LOCAL, **kw)
+    np.testing.assert_allclose(hist + loc, full, rtol=1e-12, atol=1e-14 * np.abs(full).max())
+
+
+def test_coincident_self_term_is_the_r_to_zero_limit_of_the_history():
+    # the windowed self history at r = 0 is the r -> 0 limit of the history component
+    sig = one(FAMILY_E, A=1.0, t0=0.5, w=25.0)
+    delta, b = 0.3, math.log(1e7)
+    t = 2.2
+    at0 = u1((0.2, 0.2), (0.2, 0.2), t, sig, self_mode=1, delta=delta, b=b)
+    near0 = u1((0.2, 0.2), (0.2 + 1e-9, 0.2), t, sig, window=oracle.WIN_HISTORY, delta=delta, b=b)
+    assert at0 == pytest.approx(near0, rel=1e-8)
+    # and it is excluded when self_mode = 0 (eq. exactSol omits r_j = 0)
+    assert u1((0.2, 0.2), (0.2, 0.2), t, sig) == 0.0
+
+
+def test_thread_count_does_not_change_the_sum():
+    w = config(0)
+    a = oracle.u_workload(w, [3, 7], [4.0, 8.0], nthreads=1)
+    b = oracle.u_workload(w, [3, 7], [4.0, 8.0], nthreads=4)
+    assert np.array_equal(a, b)
