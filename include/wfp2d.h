@@ -1,0 +1,191 @@
+/*
+ * wfp2d — per-time-step evaluation of 2D free-space wave potentials of many
+ * point sources by truncated-kernel windowed Fourier projection (TK-WFP),
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. 1, eqs. wave2d, solnRep, Green, pointSources): M point sources
+ * y_j and Nx targets x_i in B = [-1,1]^2, wave speed 1, signatures sigma_j(t)
+ * with sigma_j(t) = 0 for t <= 0, sampled at t_n = n dt.  The library returns
+ *     u(x_i, t) = sum_j int_0^t G(x_i - y_j, t - tau) sigma_j(tau) dtau,
+ *     G(x, t) = H(t - |x|) / (2 pi sqrt(t^2 - |x|^2)),
+ * at every step to the tolerance eps, using the three-way split of eq. split:
+ * a local part by singular quadrature (Sec. 6), a near history by the Fourier
+ * recurrence of Sec. 4, and a far history by the sum-of-exponentials
+ * recurrence of Sec. 5, with one type-1 and one type-2 non-uniform FFT per step.
+ *
+ * Conventions for every entry point
+ *   - Return value: a wfp2d_status; WFP2D_OK (0) on success, a negative code
+ *     otherwise.  Nothing crosses the ABI as an exception.  wfp2d_last_error
+ *     gives a message for the most recent failure.
+ *   - Device pointers (sigma, u) are borrowed for the call only and used in
+ *     stream order on the plan's stream; the caller keeps them alive until that
+ *     stream has passed the call.  Host pointers are read during the call only.
+ *   - A plan is used by one host thread at a time; calls on different plans
+ *     are independent.
+ *   - Arrays of points are row-major [n][2] float64 (x then y).
+ */
+#ifndef WFP2D_H
+#define WFP2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wfp2d_plan_s *wfp2d_plan;
+
+typedef enum {
+    WFP2D_OK = 0,
+    WFP2D_ERR_ARG = -1,         /* bad size, pointer or parameter */
+    WFP2D_ERR_DOMAIN = -2,      /* a point outside B = [-1,1]^2 */
+    WFP2D_ERR_INFEASIBLE = -3,  /* parameters violate eq. dt, SOE validity, or device memory */
+    WFP2D_ERR_NOMEM = -4,       /* device or host allocation failed */
+    WFP2D_ERR_DEVICE = -5,      /* a HIP runtime call failed */
+    WFP2D_ERR_STATE = -6        /* call out of order (e.g. on a destroyed plan) */
+} wfp2d_status;
+
+enum { WFP2D_PREC_FP64 = 0, WFP2D_PREC_MIXED = 1 };
+
+typedef struct {
+    /* WFP2D_PREC_MIXED (default): spreading, FFTs, the Fourier-coefficient
+     * history rings and interpolation in FP32; near/far recurrence state, the
+     * far-history sums and the local quadrature in FP64.
+     * WFP2D_PREC_FP64: everything in FP64. */
+    int32_t precision;
+    /* p, the order of the time interpolation of sigma in the local part
+     * (Sec. 6, eq. sigInterp); default 20 (Sec. 5). */
+    int32_t interp_order;
+    /* Delay, in steps, between the newest ingested sample and the time at which
+     * wfp2d_evaluate reports u.  -1 (default) = ceil(p/2) - 1, which lets every
+     * interpolation stencil of the local part be centred.  0 = report u at the
+     * newest step with stencils clamped one-sided near zero delay. */
+    int32_t lookahead;
+    double Delta;     /* radial blending width of the truncated kernel (eq. TKdef); default 1 (Sec. 5) */
+    double a;         /* near/far split margin, A+ = A + a (eq. Ap); 0 = rule max(1, delta + ln(1e15)/lambda_max) */
+    double Kf;        /* far-history Fourier cutoff (eq. ufhApprox); default 80 (Sec. 5) */
+    double b_Delta;   /* shape parameter of the radial blend; default 30 (reproduces Table 1) */
+    double nufft_tol; /* 0 = default (1e-7 mixed, 1e-11 FP64) */
+    int64_t max_steps;/* steps the plan will be run for; 0 = unchecked.  Used to check the
+                         sum-of-exponentials validity range T <~ 3e4 (Sec. 2.3). */
+    int32_t device;   /* HIP device ordinal */
+    void *stream;     /* hipStream_t for every launch (NULL = default stream) */
+} wfp2d_opts;
+
+typedef struct {
+    double dt, delta, b, A, Aplus, a, dk, K, Kf, Kmax;
+    int64_t LA;            /* (A+ - delta)/dt, an integer by construction */
+    int64_t R;             /* Fourier grid half-width: modes n in [-R, R]^2 */
+    int64_t n_modes;       /* stored half-disk modes |n dk| <= Kmax */
+    int64_t n_near;        /* of those, near-history modes |n dk| <= K */
+    int64_t n_far;         /* far-history modes |n dk| <= Kf */
+    int64_t n_far_classes; /* distinct |n|^2 among far modes */
+    int64_t nf;            /* fine (oversampled) FFT grid size per dimension */
+    int64_t band;          /* occupied rows/columns of the fine grid */
+    int64_t fft_q, fft_p;  /* nf = fft_p * fft_q, fft_q a power of two */
+    int32_t nufft_w;       /* spreading kernel width in grid points */
+    int32_t W, p, lookahead, n_levels; /* window steps, interp order, delay, sigma levels in the local part */
+    int32_t level_min;     /* most negative delay level used by the local part (= -lookahead) */
+    int32_t n_subpanels, cheb_degree;
+    int64_t M, Nx;
+    int64_t n_local_pairs; /* source-target pairs with 0 < r < delta */
+    int64_t sigma_depth;   /* slots in the sigma history ring */
+    int64_t bytes_device;  /* device memory held by the plan */
+    int64_t steps_ingested;/* number of wfp2d_step calls so far */
+    int64_t step_reported; /* n such that wfp2d_evaluate returns u(t_n) (<= 0: zero field) */
+    int32_t precision;
+} wfp2d_info;
+
+/* Fill *opts with the defaults listed above.  Never fails for a valid pointer. */
+wfp2d_status wfp2d_default_opts(wfp2d_opts *opts);
+
+/*
+ * Create a plan (Secs. 3-6; parameters by eqs. W, A, Ap, dk, K, dt).
+ *   M, src_xy  : sources, host pointer [M][2] float64, each in [-1,1]^2.
+ *   Nx, tgt_xy : targets, host pointer [Nx][2] float64, each in [-1,1]^2; may
+ *                alias src_xy.  A target that coincides with a source omits
+ *                that pair from the local part (eq. ul1 requires r > 0) and
+ *                keeps its smooth windowed history in the Fourier part.
+ *   dt         : time step (> 0).  window_W: the paper's W, delta = W dt (eq. W).
+ *   tol        : eps in (1e-15, 1e-2); b = ln(1/eps) (Sec. 2.1).
+ *   opts       : NULL for defaults.
+ * Copies the coordinates; the caller may free them on return.  Allocates all
+ * device memory of the plan (freed by wfp2d_destroy); step and evaluate never
+ * allocate.  Errors: ERR_ARG (sizes, dt, tol, W), ERR_DOMAIN (a point outside
+ * B), ERR_INFEASIBLE (pi - 2b/W <= 0, so no time step satisfies eq. dt; or
+ * max_steps*dt beyond the SOE validity range; or not enough device memory),
+ * ERR_NOMEM, ERR_DEVICE.  On error *out is set to NULL.
+ */
+wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_t Nx,
+                        const double *tgt_xy, double dt, int32_t window_W, double tol,
+                        const wfp2d_opts *opts);
+
+/*
+ * Advance one time step (Sec. 4.3, eqs. alphakEvolution, hggrid; Sec. 5,
+ * eqs. betaEvolution, beta).  sigma: device pointer [M] float64,
+ * sigma[j] = sigma_j(t_n) for the n-th call (n = 1, 2, ...), in the order of
+ * src_xy.  Ingests the sample, then (once n > lookahead) runs the packed
+ * type-1 NUFFT of the current and lagged samples, the near-history update of
+ * every Fourier mode and the far-history sum-of-exponentials update, leaving
+ * the combined Fourier coefficients of u_h(t_{n - lookahead}).
+ * Errors: ERR_ARG (NULL), ERR_STATE, ERR_DEVICE.
+ */
+wfp2d_status wfp2d_step(wfp2d_plan plan, const double *sigma);
+
+/*
+ * Write u(x_i, t_m), m = (steps so far) - lookahead, into u: device pointer
+ * [Nx] float64 in the order of tgt_xy.  u = u_h + u_l: the type-2 NUFFT of
+ * the Fourier coefficients (eqs. uhtraptrunc, ufhApprox) plus the local part
+ * (eq. ul_GL with the interpolation of eq. sigInterp).  For m <= 0 it writes
+ * zeros (zero initial data, eq. wave2d).  Errors: ERR_ARG, ERR_STATE, ERR_DEVICE.
+ */
+wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u);
+
+/* Derived parameters and sizes of a plan.  Errors: ERR_ARG. */
+wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info);
+
+/* Release every resource of the plan (waits for its stream).  NULL is a no-op. */
+wfp2d_status wfp2d_destroy(wfp2d_plan plan);
+
+/* Message for the last failure on this plan, or of the last failed wfp2d_init
+ * when plan is NULL.  The string stays valid until the next call on the plan. */
+const char *wfp2d_last_error(wfp2d_plan plan);
+
+/* Stage read-back for tests (synchronises the plan's stream).  what:
+ *   1 = S(k, t_m) of the newest near-ring slot, 2 = S(k, t_{m - LA}) of the newest lag slot,
+ *   3 = combined coefficients (dk/2pi)^2 (alpha + alpha_F) at t_m,
+ *   (each complex, packed half-disk order of wfp2d_debug_modes, in the plan's
+ *    FP32 (mixed) or FP64 precision, interleaved re/im);
+ *   4 = u_h at t_m, 5 = u_l at t_m (float64 [Nx], target order);
+ *   6 = the stored modes (n_x, n_y) as int32 pairs [n_modes][2].
+ * dst: host pointer of at least *bytes bytes; on return *bytes = bytes written.
+ * Errors: ERR_ARG (unknown what, short buffer), ERR_DEVICE. */
+wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t *bytes);
+
+/*
+ * Host-only evaluation of the plan's precomputation, without a device (for
+ * tests of the set-up numerics).  All pointers are host pointers; nothing is
+ * allocated on a device.  what:
+ *   1 derived parameters: in = {dt, W, tol, p, lookahead, Delta, a, Kf}
+ *     (n_in = 8); out = {delta, b, A, Aplus, a, dk, K, Kmax, LA, R, lookahead,
+ *     N} (n_out >= 12).  Rules of eqs. W, A, Ap, dk, K.
+ *   2 sum-of-exponentials nodes (Sec. 2.3): out = {lambda_1..640, q_1..640}.
+ *   3 Hankel coefficients H_l(kappa; A) of eq. H: in = {A, Delta, b_Delta,
+ *     kappa_1..kappa_k}; out = [k][640].
+ *   4 local weights eta_d(r) by direct quadrature (Sec. 6): in = {dt, W, p,
+ *     lookahead, tol, r_1..r_k}; out = [k][n_levels] (levels d = -lookahead...).
+ *   5 the same weights from the plan's Chebyshev tables (as the kernels
+ *     evaluate them): same in/out as 4.
+ *   6 blending function (eq. KBblending): in = {width, b, t_1..t_k};
+ *     out = [k][2] = (phi, phi').
+ * Returns ERR_ARG for an unknown what, short buffers or bad parameters; on
+ * success out_count (if not NULL) receives the number of doubles written. */
+wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, double *out, int64_t n_out,
+                             int64_t *out_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WFP2D_H */

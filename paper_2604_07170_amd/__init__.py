@@ -1,0 +1,207 @@
+"""Python binding of the wfp2d HIP library (gfx950): 2D wave potentials by TK-WFP.
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels (libwfp2d.so, built in-tree by ``paper_2604_07170_amd.build``).  If the
+library is missing this module raises; there is no CPU fallback.
+
+Typical use::
+
+    plan = Wfp2d(src_xy, tgt_xy, dt, W, tol)          # numpy float64 [n][2]
+    for n in range(1, nt + 1):
+        plan.step(sigma_n)                            # torch float64 cuda [M]
+        u = plan.evaluate()                           # torch float64 cuda [Nx], u(t_{n - lookahead})
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwfp2d.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "wfp2d.h")
+
+PREC_FP64, PREC_MIXED = 0, 1
+STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_DOMAIN", -3: "ERR_INFEASIBLE", -4: "ERR_NOMEM",
+          -5: "ERR_DEVICE", -6: "ERR_STATE"}
+
+
+class Wfp2dError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("interp_order", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+                ("Delta", ctypes.c_double), ("a", ctypes.c_double), ("Kf", ctypes.c_double),
+                ("b_Delta", ctypes.c_double), ("nufft_tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_double) for n in ("dt", "delta", "b", "A", "Aplus", "a", "dk", "K", "Kf", "Kmax")]
+                + [(n, ctypes.c_int64) for n in ("LA", "R", "n_modes", "n_near", "n_far", "n_far_classes", "nf",
+                                                 "band", "fft_q", "fft_p")]
+                + [("nufft_w", ctypes.c_int32), ("W", ctypes.c_int32), ("p", ctypes.c_int32),
+                   ("lookahead", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("level_min", ctypes.c_int32),
+                   ("n_subpanels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32)]
+                + [(n, ctypes.c_int64) for n in ("M", "Nx", "n_local_pairs", "sigma_depth", "bytes_device",
+                                                 "steps_ingested", "step_reported")]
+                + [("precision", ctypes.c_int32)])
+
+
+_lib = None
+
+
+def load_library():
+    """Load libwfp2d.so (raise if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_07170_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, d, i32, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.wfp2d_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.wfp2d_init.argtypes = [ctypes.POINTER(vp), i64, dp, i64, dp, d, i32, d, ctypes.POINTER(Opts)]
+    lib.wfp2d_step.argtypes = [vp, vp]
+    lib.wfp2d_evaluate.argtypes = [vp, vp]
+    lib.wfp2d_query.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.wfp2d_destroy.argtypes = [vp]
+    lib.wfp2d_last_error.argtypes = [vp]
+    lib.wfp2d_last_error.restype = ctypes.c_char_p
+    lib.wfp2d_debug_copy.argtypes = [vp, i32, vp, ctypes.POINTER(i64)]
+    lib.wfp2d_host_eval.argtypes = [i32, dp, i64, dp, i64, ctypes.POINTER(i64)]
+    for f in ("wfp2d_default_opts", "wfp2d_init", "wfp2d_step", "wfp2d_evaluate", "wfp2d_query", "wfp2d_destroy",
+              "wfp2d_debug_copy", "wfp2d_host_eval"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def host_eval(what: int, inputs, n_out: int) -> np.ndarray:
+    """Host-only precomputation routines of the plan (see wfp2d_host_eval)."""
+    lib = load_library()
+    x = np.ascontiguousarray(np.asarray(inputs, np.float64).ravel())
+    out = np.zeros(int(n_out), np.float64)
+    cnt = ctypes.c_int64(0)
+    rc = lib.wfp2d_host_eval(int(what), _dp(x), x.size, _dp(out), out.size, ctypes.byref(cnt))
+    if rc != 0:
+        raise Wfp2dError(rc, lib.wfp2d_last_error(None).decode())
+    return out[: cnt.value]
+
+
+def derive_params(dt, W, tol, p=20, lookahead=-1, Delta=1.0, a=0.0, Kf=80.0) -> dict:
+    v = host_eval(1, [dt, W, tol, p, lookahead, Delta, a, Kf], 12)
+    keys = ("delta", "b", "A", "Aplus", "a", "dk", "K", "Kmax", "LA", "R", "lookahead", "N")
+    out = dict(zip(keys, v.tolist()))
+    for k in ("LA", "R", "lookahead", "N"):
+        out[k] = int(round(out[k]))
+    return out
+
+
+@dataclass
+class StageNames:
+    S_CUR: int = 1
+    S_LAG: int = 2
+    ALPHA: int = 3
+    U_H: int = 4
+    U_L: int = 5
+    MODES: int = 6
+
+
+STAGE = StageNames()
+
+
+class Wfp2d:
+    """One plan: sources/targets fixed at construction, one step per sample."""
+
+    def __init__(self, src_xy, tgt_xy, dt: float, W: int, tol: float = 1e-7, *, precision: str = "mixed",
+                 interp_order: int = 20, lookahead: int = -1, Delta: float = 1.0, a: float = 0.0, Kf: float = 80.0,
+                 b_Delta: float = 30.0, nufft_tol: float = 0.0, max_steps: int = 0, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        src = np.ascontiguousarray(np.asarray(src_xy, np.float64).reshape(-1, 2))
+        tgt = np.ascontiguousarray(np.asarray(tgt_xy, np.float64).reshape(-1, 2))
+        o = Opts()
+        self.lib.wfp2d_default_opts(ctypes.byref(o))
+        o.precision = PREC_MIXED if precision == "mixed" else PREC_FP64
+        o.interp_order, o.lookahead = int(interp_order), int(lookahead)
+        o.Delta, o.a, o.Kf, o.b_Delta, o.nufft_tol = float(Delta), float(a), float(Kf), float(b_Delta), float(nufft_tol)
+        o.max_steps, o.device = int(max_steps), int(device)
+        self.device = torch.device("cuda", int(device))
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        o.stream = ctypes.c_void_p(int(stream.cuda_stream))
+        h = ctypes.c_void_p()
+        rc = self.lib.wfp2d_init(ctypes.byref(h), src.shape[0], _dp(src), tgt.shape[0], _dp(tgt), float(dt), int(W),
+                                 float(tol), ctypes.byref(o))
+        if rc != 0:
+            raise Wfp2dError(rc, self.lib.wfp2d_last_error(None).decode())
+        self.h = h
+        self.M, self.Nx = src.shape[0], tgt.shape[0]
+        self._keep = []
+
+    # -- helpers --
+    def _check(self, rc):
+        if rc != 0:
+            raise Wfp2dError(rc, self.lib.wfp2d_last_error(self.h).decode())
+
+    def info(self) -> dict:
+        inf = Info()
+        self._check(self.lib.wfp2d_query(self.h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in Info._fields_}
+
+    # -- the hot path --
+    def step(self, sigma):
+        t = self._torch
+        if not (isinstance(sigma, t.Tensor) and sigma.is_cuda and sigma.dtype == t.float64 and sigma.numel() == self.M):
+            raise ValueError("sigma must be a float64 CUDA tensor with M elements")
+        sigma = sigma.contiguous()
+        self._keep = [sigma]
+        self._check(self.lib.wfp2d_step(self.h, ctypes.c_void_p(sigma.data_ptr())))
+
+    def evaluate(self, out=None):
+        t = self._torch
+        if out is None:
+            out = t.empty(self.Nx, dtype=t.float64, device=self.device)
+        if not (out.is_cuda and out.dtype == t.float64 and out.numel() == self.Nx and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 CUDA tensor with Nx elements")
+        self._check(self.lib.wfp2d_evaluate(self.h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def debug(self, what: int) -> np.ndarray:
+        inf = self.info()
+        if what in (STAGE.U_H, STAGE.U_L):
+            buf = np.zeros(self.Nx, np.float64)
+        elif what == STAGE.MODES:
+            buf = np.zeros((inf["n_modes"], 2), np.int32)
+        else:
+            real = np.float32 if inf["precision"] == PREC_MIXED else np.float64
+            buf = np.zeros(2 * inf["n_modes"], real)
+        nb = ctypes.c_int64(buf.nbytes)
+        self._check(self.lib.wfp2d_debug_copy(self.h, int(what), buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nb)))
+        if what in (STAGE.S_CUR, STAGE.S_LAG, STAGE.ALPHA):
+            return buf[0::2].astype(np.float64) + 1j * buf[1::2].astype(np.float64)
+        return buf
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.wfp2d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

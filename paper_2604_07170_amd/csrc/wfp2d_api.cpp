@@ -1,0 +1,763 @@
+// Plan construction, step / evaluate orchestration and the C ABI of wfp2d.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "wfp2d_internal.h"
+#include "wfp2d_tables.h"
+
+struct wfp2d_plan_s {
+    wfp2d::Plan p;
+};
+
+namespace wfp2d {
+
+struct Failure {
+    wfp2d_status code;
+    std::string msg;
+};
+
+[[noreturn]] static void fail(wfp2d_status code, const std::string &msg) { throw Failure{code, msg}; }
+
+static void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) fail(WFP2D_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+T *Plan::alloc(int64_t count)
+{
+    void *ptr = nullptr;
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(WFP2D_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    allocs.push_back(ptr);
+    bytes_device += (int64_t)bytes;
+    hip_check(hipMemset(ptr, 0, bytes), "hipMemset");
+    return (T *)ptr;
+}
+
+Plan::~Plan()
+{
+    if (stream) (void)hipStreamSynchronize(stream);
+    else (void)hipDeviceSynchronize();
+    for (void *ptr : allocs) (void)hipFree(ptr);
+}
+
+template <class T>
+static void upload(T *dst, const std::vector<T> &src)
+{
+    if (src.empty()) return;
+    hip_check(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+}
+
+static int64_t next_pow2(int64_t v)
+{
+    int64_t q = 1;
+    while (q < v) q <<= 1;
+    return q;
+}
+
+// convert a host FP64 vector to the plan's real type and upload into a fresh buffer
+static void *upload_real(Plan &p, const std::vector<double> &v)
+{
+    if (p.precision == WFP2D_PREC_MIXED) {
+        std::vector<float> f(v.begin(), v.end());
+        float *d = p.alloc<float>((int64_t)f.size());
+        upload(d, f);
+        return d;
+    }
+    double *d = p.alloc<double>((int64_t)v.size());
+    upload(d, v);
+    return d;
+}
+
+static void build(Plan &p, const double *src_xy, const double *tgt_xy)
+{
+    hip_check(hipSetDevice(p.device), "hipSetDevice");
+    const int64_t M = p.M, Nx = p.Nx;
+    p.sizeof_real = (p.precision == WFP2D_PREC_MIXED) ? 4 : 8;
+
+    // ---------------- parameters ----------------
+    Params P = derive_params(p.dt, p.W, p.tol, p.Delta, p.a, p.Kf, p.p, p.lookahead);
+    if (!(M_PI - 2.0 * P.b / p.W > 0.0))
+        fail(WFP2D_ERR_INFEASIBLE, "pi - 2b/W <= 0: no time step satisfies eq. dt for this W and tol");
+    p.b = P.b;
+    p.delta = P.delta;
+    p.A = P.A;
+    p.Aplus = P.Aplus;
+    p.a = P.a;
+    p.dk = P.dk;
+    p.K = P.K;
+    p.Kmax = P.Kmax;
+    p.LA = P.LA;
+    p.lookahead = P.lookahead;
+    if (p.LA < p.W + p.p) fail(WFP2D_ERR_INFEASIBLE, "time step too large for the near-history window");
+    const int64_t R = P.R, N = 2 * R + 1;
+
+    Geom &g = p.g;
+    g.M = M;
+    g.Nx = Nx;
+    g.W = p.W;
+    g.LA = (int32_t)p.LA;
+    g.dt = p.dt;
+    g.dk = p.dk;
+    g.K = p.K;
+    g.Kf = p.Kf;
+    g.Kmax = p.Kmax;
+    g.Rd2 = (p.Kmax / p.dk) * (p.Kmax / p.dk);
+    g.R = (int32_t)R;
+    g.N = (int32_t)N;
+
+    // ---------------- NUFFT grid ----------------
+    double tol_nufft = p.nufft_tol > 0 ? p.nufft_tol : (p.precision == WFP2D_PREC_MIXED ? 1e-7 : 1e-11);
+    int w = (int)std::ceil(std::log10(1.0 / tol_nufft)) + 1;
+    w = std::max(4, std::min(16, w));
+    p.es_beta = 2.30 * w;
+    const int64_t qmax = (p.precision == WFP2D_PREC_MIXED) ? 8192 : 4096;
+    int64_t best_nf = -1;
+    for (int P_ = 1; P_ <= 3; ++P_) {
+        int64_t Q = std::max<int64_t>(64, next_pow2((2 * N + P_ - 1) / P_));
+        int64_t nf = P_ * Q;
+        double gmax = p.dk * (double)nf / (2.0 * M_PI);
+        int64_t lmin = (int64_t)std::ceil(-gmax - 0.5 * w);
+        int64_t lmax = (int64_t)std::floor(gmax + 0.5 * w);
+        int64_t Lb = lmax - lmin + 1;
+        int64_t Lpad = (Lb + kTile - 1) / kTile * kTile;
+        if (Lpad > Q || Q > qmax) continue;
+        if (best_nf < 0 || nf < best_nf) {
+            best_nf = nf;
+            g.nf = (int32_t)nf;
+            g.P = P_;
+            g.Q = (int32_t)Q;
+            g.lmin = (int32_t)lmin;
+            g.Lpad = (int32_t)Lpad;
+        }
+    }
+    if (best_nf < 0) fail(WFP2D_ERR_INFEASIBLE, "Fourier grid too large for the single-workgroup FFT");
+    g.w = w;
+    g.ntx = g.Lpad / kTile;
+
+    // ---------------- modes: packed half disk, column-major in nx ----------------
+    p.col_off.assign(R + 2, 0);
+    p.col_ny0.assign(R + 1, 0);
+    for (int64_t nx = 0; nx <= R; ++nx) {
+        double rem = g.Rd2 - (double)(nx * nx);
+        int64_t h = rem >= 0 ? (int64_t)std::floor(std::sqrt(rem)) : -1;
+        while (h >= 0 && (double)((h + 1) * (h + 1) + nx * nx) <= g.Rd2) ++h;
+        while (h >= 0 && (double)(h * h + nx * nx) > g.Rd2) --h;
+        int64_t cnt = h < 0 ? 0 : (nx == 0 ? h + 1 : 2 * h + 1);
+        p.col_ny0[nx] = (int32_t)(nx == 0 ? 0 : -h);
+        p.col_off[nx + 1] = p.col_off[nx] + (int32_t)cnt;
+        for (int64_t off = 0; off < cnt; off += kChunk)
+            p.chunks.push_back(ModeChunk{(int32_t)nx, (int32_t)(p.col_ny0[nx] + off),
+                                         (int32_t)(p.col_off[nx] + off), (int32_t)std::min<int64_t>(kChunk, cnt - off)});
+    }
+    p.n_modes = p.col_off[R + 1];
+    p.n_chunks = (int64_t)p.chunks.size();
+    std::vector<int32_t> far_pk, far_key;
+    const double K2 = p.K * p.K, Kf2 = p.Kf * p.Kf, dk2 = p.dk * p.dk;
+    for (int64_t nx = 0; nx <= R; ++nx)
+        for (int64_t i = 0; i < p.col_off[nx + 1] - p.col_off[nx]; ++i) {
+            int64_t ny = p.col_ny0[nx] + i;
+            int64_t key = nx * nx + ny * ny;
+            if ((double)key * dk2 <= K2) ++p.n_near;
+            if ((double)key * dk2 <= Kf2) {
+                far_pk.push_back((int32_t)(p.col_off[nx] + i));
+                far_key.push_back((int32_t)key);
+            }
+        }
+    p.n_far = (int64_t)far_pk.size();
+    std::vector<int32_t> keys(far_key);
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    p.n_classes = (int64_t)keys.size();
+    std::vector<int32_t> far_cls(p.n_far);
+    for (int64_t f = 0; f < p.n_far; ++f)
+        far_cls[f] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), far_key[f]) - keys.begin());
+
+    // ---------------- geometry: sort by local cell ----------------
+    p.ncell = std::max(1, (int)std::floor(2.0 / p.delta));
+    p.cell_h = 2.0 / p.ncell;
+    auto cell_of = [&](double x, double y) {
+        int cx = std::min(p.ncell - 1, std::max(0, (int)std::floor((x + 1.0) / p.cell_h)));
+        int cy = std::min(p.ncell - 1, std::max(0, (int)std::floor((y + 1.0) / p.cell_h)));
+        return cy * p.ncell + cx;
+    };
+    std::vector<int32_t> scell(M), sperm(M);
+    for (int64_t j = 0; j < M; ++j) scell[j] = cell_of(src_xy[2 * j], src_xy[2 * j + 1]);
+    std::iota(sperm.begin(), sperm.end(), 0);
+    std::stable_sort(sperm.begin(), sperm.end(), [&](int32_t a, int32_t b) { return scell[a] < scell[b]; });
+    std::vector<int32_t> cell_start((size_t)p.ncell * p.ncell + 1, 0);
+    for (int64_t j = 0; j < M; ++j) cell_start[scell[j] + 1]++;
+    for (size_t c = 1; c < cell_start.size(); ++c) cell_start[c] += cell_start[c - 1];
+    std::vector<int32_t> tcell(Nx), tperm(Nx), trank(Nx);
+    for (int64_t i = 0; i < Nx; ++i) tcell[i] = cell_of(tgt_xy[2 * i], tgt_xy[2 * i + 1]);
+    std::iota(tperm.begin(), tperm.end(), 0);
+    std::stable_sort(tperm.begin(), tperm.end(), [&](int32_t a, int32_t b) { return tcell[a] < tcell[b]; });
+    for (int64_t i = 0; i < Nx; ++i) trank[tperm[i]] = (int32_t)i;
+    std::vector<double2> sxy(M), txy(Nx);
+    std::vector<int32_t> tcell_sorted(Nx);
+    for (int64_t j = 0; j < M; ++j) sxy[j] = make_double2(src_xy[2 * sperm[j]], src_xy[2 * sperm[j] + 1]);
+    for (int64_t i = 0; i < Nx; ++i) {
+        txy[i] = make_double2(tgt_xy[2 * tperm[i]], tgt_xy[2 * tperm[i] + 1]);
+        tcell_sorted[i] = tcell[tperm[i]];
+    }
+
+    // spreading / interpolation kernel data, tile lists
+    const double gscale = p.dk * g.nf / (2.0 * M_PI);
+    auto kernel_data = [&](const std::vector<double2> &pts, std::vector<int2> &base, std::vector<double> &wts) {
+        const int64_t n = (int64_t)pts.size();
+        base.resize(n);
+        wts.resize((size_t)n * 2 * w);
+        for (int64_t j = 0; j < n; ++j) {
+            double gx = pts[j].x * gscale, gy = pts[j].y * gscale;
+            int64_t l0x = (int64_t)std::ceil(gx - 0.5 * w), l0y = (int64_t)std::ceil(gy - 0.5 * w);
+            base[j] = make_int2((int)(l0x - g.lmin), (int)(l0y - g.lmin));
+            if (base[j].x < 0 || base[j].y < 0 || base[j].x + w > g.Lpad || base[j].y + w > g.Lpad)
+                fail(WFP2D_ERR_DOMAIN, "point outside the spreading band");
+            for (int a2 = 0; a2 < w; ++a2) {
+                wts[(size_t)j * 2 * w + a2] = es_kernel((double)(l0x + a2) - gx, w, p.es_beta);
+                wts[(size_t)j * 2 * w + w + a2] = es_kernel((double)(l0y + a2) - gy, w, p.es_beta);
+            }
+        }
+    };
+    std::vector<int2> sbase, tbase;
+    std::vector<double> swts, twts;
+    kernel_data(sxy, sbase, swts);
+    kernel_data(txy, tbase, twts);
+    const int ntile = g.ntx * g.ntx;
+    {
+        // spreading: every source is listed in each tile its kernel support meets
+        auto tiles_of = [&](int64_t j, int &tx0, int &tx1, int &ty0, int &ty1) {
+            tx0 = sbase[j].x / kTile;
+            tx1 = (sbase[j].x + w - 1) / kTile;
+            ty0 = sbase[j].y / kTile;
+            ty1 = (sbase[j].y + w - 1) / kTile;
+        };
+        std::vector<int32_t> off(ntile + 1, 0);
+        for (int64_t j = 0; j < M; ++j) {
+            int tx0, tx1, ty0, ty1;
+            tiles_of(j, tx0, tx1, ty0, ty1);
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) off[ty * g.ntx + tx + 1]++;
+        }
+        for (int t = 0; t < ntile; ++t) off[t + 1] += off[t];
+        std::vector<int32_t> pos(off.begin(), off.end() - 1), lst(off[ntile]);
+        for (int64_t j = 0; j < M; ++j) {
+            int tx0, tx1, ty0, ty1;
+            tiles_of(j, tx0, tx1, ty0, ty1);
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) lst[pos[ty * g.ntx + tx]++] = (int32_t)j;
+        }
+        p.d_tile_off = p.alloc<int32_t>(ntile + 1);
+        upload(p.d_tile_off, off);
+        p.d_tile_src = p.alloc<int32_t>(off[ntile]);
+        upload(p.d_tile_src, lst);
+    }
+    // interpolation: each target belongs to the tile holding its kernel origin
+    {
+        std::vector<int32_t> off(ntile + 1, 0), lst(Nx);
+        for (int64_t i = 0; i < Nx; ++i) off[(tbase[i].y / kTile) * g.ntx + tbase[i].x / kTile + 1]++;
+        for (int t = 0; t < ntile; ++t) off[t + 1] += off[t];
+        std::vector<int32_t> pos(off.begin(), off.end() - 1);
+        for (int64_t i = 0; i < Nx; ++i) lst[pos[(tbase[i].y / kTile) * g.ntx + tbase[i].x / kTile]++] = (int32_t)i;
+        p.d_ttile_off = p.alloc<int32_t>(ntile + 1);
+        upload(p.d_ttile_off, off);
+        p.d_ttile_tgt = p.alloc<int32_t>(Nx);
+        upload(p.d_ttile_tgt, lst);
+    }
+
+    // ---------------- tables ----------------
+    Blend phi(p.delta, p.b, 160);
+    std::vector<double> phi_in(p.W + 1);
+    for (int l = 0; l <= p.W; ++l) phi_in[l] = phi.phi(l * p.dt);
+    phi_in[0] = 0.0;
+    phi_in[p.W] = 1.0;
+
+    std::vector<double> lam, qw;
+    soe_nodes(lam, qw);
+    std::vector<double> kap(p.n_classes);
+    for (int64_t c = 0; c < p.n_classes; ++c) kap[c] = p.dk * std::sqrt((double)keys[c]);
+    std::vector<double> H;
+    hankel_table(kap, p.A, p.Delta, p.b_Delta, lam, qw, H);
+    std::vector<double> dec(kNsoe), inj(kNsoe), chi((size_t)p.n_classes * (p.W - 1));
+    for (int l = 0; l < kNsoe; ++l) {
+        dec[l] = std::exp(-lam[l] * p.dt);
+        inj[l] = p.dt * std::exp(-lam[l] * ((double)(p.LA + p.W - 1) * p.dt - p.A));
+    }
+    for (int64_t c = 0; c < p.n_classes; ++c)
+        for (int i = 0; i < p.W - 1; ++i) {
+            double s = 0.0, wwin = 1.0 - phi_in[p.W - 1 - i];
+            for (int l = 0; l < kNsoe; ++l)
+                s += H[(size_t)c * kNsoe + l] * p.dt * std::exp(-lam[l] * ((double)(p.LA + 1 + i) * p.dt - p.A));
+            chi[(size_t)c * (p.W - 1) + i] = s * wwin;
+        }
+
+    const int lev_min = -p.lookahead;
+    LocalWeights LW(p.dt, p.W, p.p, lev_min, phi);
+    LocalTable LT = build_local_table(LW, 40, 1e-12);
+    g.nlev = LT.nlev;
+    g.lev_min = lev_min;
+    p.n_sub = (int32_t)LT.subs.size();
+    p.subs = LT.subs;
+    p.dy_base = LT.dy_base;
+    p.n_dy = LT.n_dy;
+    // sigma history: the lagged type-1 input reaches m - LA; the local part reaches m - dmax
+    int64_t dmax = lev_min + LT.nlev - 1;
+    g.sig_depth = std::max<int64_t>(p.LA, dmax) + p.lookahead + 1;
+
+    // local-pair count (reported; the local kernel finds pairs through the cell lists)
+    {
+        int64_t cnt = 0;
+        const double d2 = p.delta * p.delta;
+        for (int64_t i = 0; i < Nx; ++i) {
+            int c = tcell_sorted[i], cx = c % p.ncell, cy = c / p.ncell;
+            for (int yy = std::max(0, cy - 1); yy <= std::min(p.ncell - 1, cy + 1); ++yy)
+                for (int xx = std::max(0, cx - 1); xx <= std::min(p.ncell - 1, cx + 1); ++xx) {
+                    int cc = yy * p.ncell + xx;
+                    for (int32_t j = cell_start[cc]; j < cell_start[cc + 1]; ++j) {
+                        double dx = txy[i].x - sxy[j].x, dy = txy[i].y - sxy[j].y, r2 = dx * dx + dy * dy;
+                        if (r2 > 0.0 && r2 < d2) ++cnt;
+                    }
+                }
+        }
+        p.n_local_pairs = cnt;
+    }
+
+    // NUFFT correction and twiddles
+    std::vector<double> psihat;
+    es_fourier(w, p.es_beta, g.nf, R, psihat);
+    std::vector<double> corr(2 * N), tw(2 * (size_t)g.nf);
+    for (int64_t n = -R; n <= R; ++n) {
+        double ang = 2.0 * M_PI * (double)(n * g.lmin % g.nf) / (double)g.nf;
+        corr[2 * (n + R)] = std::cos(ang) / psihat[n + R];
+        corr[2 * (n + R) + 1] = std::sin(ang) / psihat[n + R];
+    }
+    for (int64_t j = 0; j < g.nf; ++j) {
+        tw[2 * j] = std::cos(2.0 * M_PI * (double)j / (double)g.nf);
+        tw[2 * j + 1] = std::sin(2.0 * M_PI * (double)j / (double)g.nf);
+    }
+
+    // ---------------- device memory ----------------
+    const int64_t sr = p.sizeof_real;
+    p.d_sig = p.alloc<double>(g.sig_depth * M);
+    p.d_src_perm = p.alloc<int32_t>(M);
+    upload(p.d_src_perm, sperm);
+    p.d_tgt_rank = p.alloc<int32_t>(Nx);
+    upload(p.d_tgt_rank, trank);
+    p.d_src_xy = p.alloc<double2>(M);
+    upload(p.d_src_xy, sxy);
+    p.d_tgt_xy = p.alloc<double2>(Nx);
+    upload(p.d_tgt_xy, txy);
+    p.d_src_base = p.alloc<int2>(M);
+    upload(p.d_src_base, sbase);
+    p.d_src_wts = upload_real(p, swts);
+    p.d_tgt_base = p.alloc<int2>(Nx);
+    upload(p.d_tgt_base, tbase);
+    p.d_tgt_wts = upload_real(p, twts);
+    p.d_grid = p.alloc<char>((int64_t)g.Lpad * g.Lpad * 2 * sr);
+    p.d_T1 = p.alloc<char>((int64_t)g.Lpad * N * 2 * sr);
+    p.d_F = p.alloc<char>(N * N * 2 * sr);
+    p.d_corr = upload_real(p, corr);
+    p.d_tw = upload_real(p, tw);
+    p.d_ring_cur = p.alloc<char>((int64_t)p.W * p.n_modes * 2 * sr);
+    p.d_ring_lag = p.alloc<char>((int64_t)p.W * p.n_modes * 2 * sr);
+    p.d_chunks = p.alloc<ModeChunk>(p.n_chunks);
+    upload(p.d_chunks, p.chunks);
+    p.d_col_off = p.alloc<int32_t>(R + 2);
+    upload(p.d_col_off, p.col_off);
+    p.d_col_ny0 = p.alloc<int32_t>(R + 1);
+    upload(p.d_col_ny0, p.col_ny0);
+    p.d_D = p.alloc<double2>(p.n_modes);
+    p.d_C = p.alloc<double2>(p.n_modes);
+    p.d_phi_in = p.alloc<double>(p.W + 1);
+    upload(p.d_phi_in, phi_in);
+    p.d_atot = p.alloc<char>(p.n_modes * 2 * sr);
+    p.d_far_pk = p.alloc<int32_t>(p.n_far);
+    upload(p.d_far_pk, far_pk);
+    p.d_far_cls = p.alloc<int32_t>(p.n_far);
+    upload(p.d_far_cls, far_cls);
+    p.d_H = p.alloc<double>(p.n_classes * kNsoe);
+    upload(p.d_H, H);
+    p.d_chi = p.alloc<double>(p.n_classes * (p.W - 1));
+    upload(p.d_chi, chi);
+    p.d_dec = p.alloc<double>(kNsoe);
+    upload(p.d_dec, dec);
+    p.d_inj = p.alloc<double>(kNsoe);
+    upload(p.d_inj, inj);
+    p.d_B = p.alloc<double2>(p.n_far * kNsoe);
+    p.d_T2 = p.alloc<char>((R + 1) * (int64_t)g.Lpad * 2 * sr);
+    p.d_cgrid = p.alloc<char>((int64_t)g.Lpad * g.Lpad * sr);
+    p.d_uh = p.alloc<double>(Nx);
+    p.d_ul = p.alloc<double>(Nx);
+    p.d_cell_start = p.alloc<int32_t>((int64_t)cell_start.size());
+    upload(p.d_cell_start, cell_start);
+    p.d_tgt_cell = p.alloc<int32_t>(Nx);
+    upload(p.d_tgt_cell, tcell_sorted);
+    p.d_subs = p.alloc<SubPanel>(p.n_sub);
+    upload(p.d_subs, LT.subs);
+    p.d_cheb = p.alloc<double>((int64_t)LT.coef.size());
+    upload(p.d_cheb, LT.coef);
+    p.d_panel_base = p.alloc<int32_t>(p.W);
+    upload(p.d_panel_base, LT.panel_base);
+    p.d_panel_l2n = p.alloc<int32_t>(p.W);
+    upload(p.d_panel_l2n, LT.panel_l2n);
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize after set-up");
+}
+
+static void do_step(Plan &p, const double *sigma)
+{
+    hip_check(hipSetDevice(p.device), "hipSetDevice");
+    const Geom &g = p.g;
+    p.steps += 1;
+    hip_check(launch_ingest(p, sigma, p.steps % g.sig_depth), "ingest");
+    const int64_t m = p.steps - p.lookahead;
+    if (m < 1) return;
+    auto md = [](int64_t a, int64_t b) { return ((a % b) + b) % b; };
+    hip_check(launch_spread(p, md(m, g.sig_depth), md(m - p.LA, g.sig_depth)), "spread");
+    hip_check(launch_fft_rows1(p), "fft rows (type 1)");
+    hip_check(launch_fft_cols1(p), "fft columns (type 1)");
+    hip_check(launch_split(p, md(m, p.W), md(m - p.LA, p.W)), "hermitian split");
+    hip_check(launch_near(p, m), "near-history update");
+    hip_check(launch_far(p, m), "far-history update");
+}
+
+static void do_evaluate(Plan &p, double *u)
+{
+    hip_check(hipSetDevice(p.device), "hipSetDevice");
+    const int64_t m = p.steps - p.lookahead;
+    if (m < 1) {
+        hip_check(launch_combine(p, u, 1), "combine");
+        return;
+    }
+    hip_check(launch_fft_cols2(p), "fft columns (type 2)");
+    hip_check(launch_fft_rows2(p), "fft rows (type 2)");
+    hip_check(launch_interp(p), "interpolation");
+    hip_check(launch_local(p, m), "local part");
+    hip_check(launch_combine(p, u, 0), "combine");
+}
+
+}  // namespace wfp2d
+
+using namespace wfp2d;
+
+static std::string g_init_error;
+
+#define WFP2D_GUARD(plan_ptr, ...)                                         \
+    try {                                                                  \
+        __VA_ARGS__;                                                       \
+    } catch (const Failure &f) {                                           \
+        if (plan_ptr) (plan_ptr)->p.err = f.msg;                           \
+        else g_init_error = f.msg;                                         \
+        return f.code;                                                     \
+    } catch (const std::bad_alloc &) {                                     \
+        if (plan_ptr) (plan_ptr)->p.err = "host allocation failed";        \
+        else g_init_error = "host allocation failed";                      \
+        return WFP2D_ERR_NOMEM;                                            \
+    } catch (const std::exception &e) {                                    \
+        if (plan_ptr) (plan_ptr)->p.err = e.what();                        \
+        else g_init_error = e.what();                                      \
+        return WFP2D_ERR_DEVICE;                                           \
+    }
+
+extern "C" {
+
+wfp2d_status wfp2d_default_opts(wfp2d_opts *o)
+{
+    if (!o) return WFP2D_ERR_ARG;
+    std::memset(o, 0, sizeof *o);
+    o->precision = WFP2D_PREC_MIXED;
+    o->interp_order = 20;
+    o->lookahead = -1;
+    o->Delta = 1.0;
+    o->a = 0.0;
+    o->Kf = 80.0;
+    o->b_Delta = 30.0;
+    o->nufft_tol = 0.0;
+    o->max_steps = 0;
+    o->device = 0;
+    o->stream = nullptr;
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_t Nx, const double *tgt_xy,
+                        double dt, int32_t window_W, double tol, const wfp2d_opts *opts)
+{
+    if (out) *out = nullptr;
+    wfp2d_plan_s *h = nullptr;
+    try {
+        if (!out || !src_xy || !tgt_xy) fail(WFP2D_ERR_ARG, "NULL pointer argument");
+        if (M <= 0 || Nx <= 0 || M > 2000000000LL || Nx > 2000000000LL) fail(WFP2D_ERR_ARG, "M and Nx must be in [1, 2e9]");
+        if (!(dt > 0.0) || !std::isfinite(dt)) fail(WFP2D_ERR_ARG, "dt must be positive and finite");
+        if (window_W < 2 || window_W > 4096) fail(WFP2D_ERR_ARG, "W must be in [2, 4096]");
+        if (!(tol > 1e-15 && tol < 1e-2)) fail(WFP2D_ERR_ARG, "tol must be in (1e-15, 1e-2)");
+        wfp2d_opts o;
+        wfp2d_default_opts(&o);
+        if (opts) o = *opts;
+        if (o.precision != WFP2D_PREC_FP64 && o.precision != WFP2D_PREC_MIXED) fail(WFP2D_ERR_ARG, "unknown precision");
+        if (o.interp_order < 2 || o.interp_order > 32) fail(WFP2D_ERR_ARG, "interp_order must be in [2, 32]");
+        if (!(o.Delta > 0.0) || !(o.Kf > 0.0) || !(o.b_Delta > 0.0) || o.a < 0.0) fail(WFP2D_ERR_ARG, "bad Delta, Kf, b_Delta or a");
+        for (int64_t i = 0; i < M; ++i)
+            if (!(std::fabs(src_xy[2 * i]) <= 1.0 && std::fabs(src_xy[2 * i + 1]) <= 1.0))
+                fail(WFP2D_ERR_DOMAIN, "source " + std::to_string(i) + " outside [-1,1]^2");
+        for (int64_t i = 0; i < Nx; ++i)
+            if (!(std::fabs(tgt_xy[2 * i]) <= 1.0 && std::fabs(tgt_xy[2 * i + 1]) <= 1.0))
+                fail(WFP2D_ERR_DOMAIN, "target " + std::to_string(i) + " outside [-1,1]^2");
+        if (!(M_PI - 2.0 * std::log(1.0 / tol) / window_W > 0.0))
+            fail(WFP2D_ERR_INFEASIBLE, "pi - 2b/W <= 0: no time step satisfies eq. dt for this W and tol");
+        if (o.max_steps > 0 && (double)o.max_steps * dt > 3.0e4)
+            fail(WFP2D_ERR_INFEASIBLE, "max_steps*dt beyond the sum-of-exponentials validity range (T <~ 3e4)");
+        h = new wfp2d_plan_s();
+        Plan &p = h->p;
+        p.M = M;
+        p.Nx = Nx;
+        p.dt = dt;
+        p.tol = tol;
+        p.W = window_W;
+        p.p = o.interp_order;
+        p.lookahead = o.lookahead;
+        p.precision = o.precision;
+        p.Delta = o.Delta;
+        p.a = o.a;
+        p.Kf = o.Kf;
+        p.b_Delta = o.b_Delta;
+        p.nufft_tol = o.nufft_tol;
+        p.device = o.device;
+        p.stream = (hipStream_t)o.stream;
+        build(p, src_xy, tgt_xy);
+        *out = h;
+        return WFP2D_OK;
+    } catch (const Failure &f) {
+        g_init_error = f.msg;
+        delete h;
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        g_init_error = "host allocation failed";
+        delete h;
+        return WFP2D_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        g_init_error = e.what();
+        delete h;
+        return WFP2D_ERR_DEVICE;
+    }
+}
+
+wfp2d_status wfp2d_step(wfp2d_plan plan, const double *sigma)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        if (!sigma) fail(WFP2D_ERR_ARG, "NULL sigma");
+        do_step(plan->p, sigma);
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        if (!u) fail(WFP2D_ERR_ARG, "NULL u");
+        do_evaluate(plan->p, u);
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
+{
+    if (!plan || !info) return WFP2D_ERR_ARG;
+    const Plan &p = plan->p;
+    std::memset(info, 0, sizeof *info);
+    info->dt = p.dt;
+    info->delta = p.delta;
+    info->b = p.b;
+    info->A = p.A;
+    info->Aplus = p.Aplus;
+    info->a = p.a;
+    info->dk = p.dk;
+    info->K = p.K;
+    info->Kf = p.Kf;
+    info->Kmax = p.Kmax;
+    info->LA = p.LA;
+    info->R = p.g.R;
+    info->n_modes = p.n_modes;
+    info->n_near = p.n_near;
+    info->n_far = p.n_far;
+    info->n_far_classes = p.n_classes;
+    info->nf = p.g.nf;
+    info->band = p.g.Lpad;
+    info->fft_q = p.g.Q;
+    info->fft_p = p.g.P;
+    info->nufft_w = p.g.w;
+    info->W = p.W;
+    info->p = p.p;
+    info->lookahead = p.lookahead;
+    info->n_levels = p.g.nlev;
+    info->level_min = p.g.lev_min;
+    info->n_subpanels = p.n_sub;
+    info->cheb_degree = kChebDeg;
+    info->M = p.M;
+    info->Nx = p.Nx;
+    info->n_local_pairs = p.n_local_pairs;
+    info->sigma_depth = p.g.sig_depth;
+    info->bytes_device = p.bytes_device;
+    info->steps_ingested = p.steps;
+    info->step_reported = p.steps - p.lookahead;
+    info->precision = p.precision;
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_destroy(wfp2d_plan plan)
+{
+    if (!plan) return WFP2D_OK;
+    delete plan;
+    return WFP2D_OK;
+}
+
+const char *wfp2d_last_error(wfp2d_plan plan)
+{
+    if (!plan) return g_init_error.c_str();
+    return plan->p.err.c_str();
+}
+
+wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t *bytes)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        if (!dst || !bytes) fail(WFP2D_ERR_ARG, "NULL argument");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+        const int64_t m = p.steps - p.lookahead;
+        auto md = [](int64_t a, int64_t b) { return ((a % b) + b) % b; };
+        const int64_t csz = 2 * p.sizeof_real * p.n_modes;
+        const void *src = nullptr;
+        int64_t n = 0;
+        std::vector<int32_t> modes;
+        switch (what) {
+        case 1: src = (const char *)p.d_ring_cur + md(m, p.W) * csz; n = csz; break;
+        case 2: src = (const char *)p.d_ring_lag + md(m - p.LA, p.W) * csz; n = csz; break;
+        case 3: src = p.d_atot; n = csz; break;
+        case 4: case 5: {
+            if (*bytes < 8 * p.Nx) fail(WFP2D_ERR_ARG, "destination too small");
+            std::vector<double> tmp(p.Nx), outv(p.Nx);
+            std::vector<int32_t> rank(p.Nx);
+            hip_check(hipMemcpy(tmp.data(), what == 4 ? p.d_uh : p.d_ul, 8 * p.Nx, hipMemcpyDeviceToHost), "copy");
+            hip_check(hipMemcpy(rank.data(), p.d_tgt_rank, 4 * p.Nx, hipMemcpyDeviceToHost), "copy");
+            for (int64_t i = 0; i < p.Nx; ++i) outv[i] = tmp[rank[i]];
+            std::memcpy(dst, outv.data(), 8 * p.Nx);
+            *bytes = 8 * p.Nx;
+            return WFP2D_OK;
+        }
+        case 6: {
+            for (int64_t nx = 0; nx <= p.g.R; ++nx)
+                for (int64_t i = 0; i < p.col_off[nx + 1] - p.col_off[nx]; ++i) {
+                    modes.push_back((int32_t)nx);
+                    modes.push_back((int32_t)(p.col_ny0[nx] + i));
+                }
+            n = 4 * (int64_t)modes.size();
+            if (*bytes < n) fail(WFP2D_ERR_ARG, "destination too small");
+            std::memcpy(dst, modes.data(), n);
+            *bytes = n;
+            return WFP2D_OK;
+        }
+        default: fail(WFP2D_ERR_ARG, "unknown stage");
+        }
+        if (*bytes < n) fail(WFP2D_ERR_ARG, "destination too small");
+        hip_check(hipMemcpy(dst, src, n, hipMemcpyDeviceToHost), "copy");
+        *bytes = n;
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, double *out, int64_t n_out,
+                             int64_t *out_count)
+{
+    try {
+        if (!in && n_in > 0) fail(WFP2D_ERR_ARG, "NULL input");
+        if (!out) fail(WFP2D_ERR_ARG, "NULL output");
+        int64_t cnt = 0;
+        auto need = [&](int64_t n) {
+            if (n_out < n) fail(WFP2D_ERR_ARG, "output too small");
+            cnt = n;
+        };
+        switch (what) {
+        case 1: {
+            if (n_in < 8) fail(WFP2D_ERR_ARG, "need 8 inputs");
+            Params P = derive_params(in[0], (int)in[1], in[2], in[5], in[6], in[7], (int)in[3], (int)in[4]);
+            need(12);
+            double v[12] = {P.delta, P.b, P.A, P.Aplus, P.a, P.dk, P.K, P.Kmax, (double)P.LA, (double)P.R,
+                            (double)P.lookahead, (double)(2 * P.R + 1)};
+            std::copy(v, v + 12, out);
+            break;
+        }
+        case 2: {
+            std::vector<double> lam, q;
+            soe_nodes(lam, q);
+            need(2 * kNsoe);
+            std::copy(lam.begin(), lam.end(), out);
+            std::copy(q.begin(), q.end(), out + kNsoe);
+            break;
+        }
+        case 3: {
+            if (n_in < 3) fail(WFP2D_ERR_ARG, "need A, Delta, b_Delta");
+            std::vector<double> lam, q, H, kap(in + 3, in + n_in);
+            soe_nodes(lam, q);
+            hankel_table(kap, in[0], in[1], in[2], lam, q, H);
+            need((int64_t)H.size());
+            std::copy(H.begin(), H.end(), out);
+            break;
+        }
+        case 4: case 5: {
+            if (n_in < 5) fail(WFP2D_ERR_ARG, "need dt, W, p, lookahead, tol");
+            const double dt = in[0], tol = in[4];
+            const int W = (int)in[1], p = (int)in[2];
+            int look = (int)in[3];
+            if (look < 0) look = (p + 1) / 2 - 1;
+            if (!(dt > 0) || W < 2 || p < 2 || !(tol > 0 && tol < 1)) fail(WFP2D_ERR_ARG, "bad local parameters");
+            Blend phi(W * dt, std::log(1.0 / tol), 160);
+            LocalWeights LW(dt, W, p, -look, phi);
+            const int64_t k = n_in - 5;
+            need(k * LW.nlev);
+            if (what == 4) {
+                for (int64_t i = 0; i < k; ++i) LW.eta(in[5 + i], out + i * LW.nlev);
+            } else {
+                LocalTable T = build_local_table(LW, 40, 1e-12);
+                for (int64_t i = 0; i < k; ++i) local_table_eval(T, dt, W, in[5 + i], out + i * LW.nlev);
+            }
+            break;
+        }
+        case 6: {
+            if (n_in < 2) fail(WFP2D_ERR_ARG, "need width, b");
+            Blend B(in[0], in[1], 160);
+            const int64_t k = n_in - 2;
+            need(2 * k);
+            for (int64_t i = 0; i < k; ++i) {
+                out[2 * i] = B.phi(in[2 + i]);
+                out[2 * i + 1] = B.dphi(in[2 + i]);
+            }
+            break;
+        }
+        default: fail(WFP2D_ERR_ARG, "unknown what");
+        }
+        if (out_count) *out_count = cnt;
+        return WFP2D_OK;
+    } catch (const Failure &f) {
+        g_init_error = f.msg;
+        return f.code;
+    } catch (const std::exception &e) {
+        g_init_error = e.what();
+        return WFP2D_ERR_ARG;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Internal declarations shared by the host side (plan set-up, C ABI) and the
+// HIP kernels of the wfp2d library.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wfp2d.h"
+
+namespace wfp2d {
+
+constexpr int kTile = 32;          // spreading / interpolation tile edge (fine-grid points)
+constexpr int kChunk = 256;        // modes per work chunk of the per-mode kernels
+constexpr int kNsoe = 640;         // SOE terms: 20 dyadic panels x 32 Gauss-Legendre nodes (Sec. 2.3)
+constexpr int kChebDeg = 16;       // Chebyshev terms per local-weight sub-panel
+
+// Work chunk of a per-mode kernel: modes [off, off+cnt) of packed column nx,
+// whose first mode has ny = ny0 (ny increases by one per mode).
+struct ModeChunk {
+    int32_t nx, ny0, off, cnt;
+};
+
+// One sub-panel of the tabulated local weights eta_d(r).
+struct SubPanel {
+    double ra, rb;   // r range
+    double c;        // > 0: Chebyshev variable in u = sqrt(c - r); 0: linear in r
+    double ua, ub;   // sqrt(c - ra), sqrt(c - rb) when c > 0
+};
+
+// Parameters every kernel needs (passed by value).
+struct Geom {
+    int64_t M, Nx;
+    int32_t W, LA, nlev, lev_min;      // levels d in [lev_min, lev_min + nlev)
+    int64_t sig_depth;                 // sigma ring slots
+    double dt, dk, K, Kf, Kmax, Rd2;   // Rd2 = (Kmax/dk)^2
+    int32_t R, N;                      // N = 2R + 1
+    int32_t nf, P, Q, lmin, Lpad, w;   // fine grid, band origin / padded size, kernel width
+    int32_t ntx;                       // tiles per band dimension
+};
+
+struct Plan;
+
+// ---- launchers (kernels file) ----
+hipError_t launch_ingest(Plan &p, const double *sigma_in, int64_t slot);
+hipError_t launch_spread(Plan &p, int64_t slot_cur, int64_t slot_lag);
+hipError_t launch_fft_rows1(Plan &p);
+hipError_t launch_fft_cols1(Plan &p);
+hipError_t launch_split(Plan &p, int64_t ring_cur, int64_t ring_lag);
+hipError_t launch_near(Plan &p, int64_t m);
+hipError_t launch_far(Plan &p, int64_t m);
+hipError_t launch_fft_cols2(Plan &p);
+hipError_t launch_fft_rows2(Plan &p);
+hipError_t launch_interp(Plan &p);
+hipError_t launch_local(Plan &p, int64_t m);
+hipError_t launch_combine(Plan &p, double *u_out, int zero);
+hipError_t launch_zero(Plan &p, void *ptr, int64_t bytes);
+
+// ---- the plan ----
+struct Plan {
+    // problem
+    int64_t M = 0, Nx = 0;
+    double dt = 0, tol = 0;
+    int32_t W = 0, p = 20, lookahead = 0, precision = 1;
+    double Delta = 1, a = 0, Kf = 80, b_Delta = 30, nufft_tol = 0;
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+
+    // derived parameters
+    double b = 0, delta = 0, A = 0, Aplus = 0, dk = 0, K = 0, Kmax = 0;
+    int64_t LA = 0;
+    Geom g{};
+    double es_beta = 0;              // exponential-of-semicircle shape
+
+    // mode tables
+    int64_t n_modes = 0, n_near = 0, n_far = 0, n_classes = 0;
+    std::vector<int32_t> col_off;    // packed offset of column nx (nx = 0..R), size R+2
+    std::vector<int32_t> col_ny0;    // first ny of column nx
+    std::vector<ModeChunk> chunks;   // near / split / alpha work list
+    int64_t n_local_pairs = 0;
+    int32_t n_sub = 0;
+    std::vector<SubPanel> subs;
+
+    // step counters
+    int64_t steps = 0;               // samples ingested
+    int64_t sizeof_real = 4;
+
+    // ---- device memory ----
+    std::vector<void *> allocs;
+    int64_t bytes_device = 0;
+    double *d_sig = nullptr;          // [sig_depth][M] float64, sorted source order
+    int32_t *d_src_perm = nullptr;    // sorted j -> caller index
+    int32_t *d_tgt_rank = nullptr;    // caller index -> sorted i
+    double2 *d_src_xy = nullptr, *d_tgt_xy = nullptr;   // sorted order
+    // spreading
+    int2 *d_src_base = nullptr;       // band-local kernel origin per sorted source
+    void *d_src_wts = nullptr;        // [M][2w] Real
+    int32_t *d_tile_off = nullptr, *d_tile_src = nullptr;
+    void *d_grid = nullptr;           // [Lpad][Lpad] complex Real
+    void *d_T1 = nullptr;             // [Lpad][N] complex Real (rows transformed)
+    void *d_F = nullptr;              // [N][N] complex Real, index [nx+R][ny+R]
+    void *d_corr = nullptr;           // [N] complex Real: e^{2 pi i n lmin/nf} / psi_hat(n)
+    void *d_tw = nullptr;             // [nf] complex Real: e^{2 pi i j / nf}
+    // rings of Fourier coefficients
+    void *d_ring_cur = nullptr;       // [W][n_modes] complex Real
+    void *d_ring_lag = nullptr;       // [W][n_modes] complex Real
+    ModeChunk *d_chunks = nullptr;
+    int32_t *d_col_off = nullptr, *d_col_ny0 = nullptr;   // packed column tables
+    int64_t n_chunks = 0;
+    double2 *d_D = nullptr, *d_C = nullptr;   // near state per packed mode
+    double *d_phi_in = nullptr;       // phi(l dt), l = 0..W
+    void *d_atot = nullptr;           // [n_modes] complex Real
+    // far history
+    int32_t *d_far_pk = nullptr, *d_far_cls = nullptr;
+    double *d_H = nullptr;            // [n_classes][640]
+    double *d_chi = nullptr;          // [n_classes][W-1]
+    double *d_dec = nullptr, *d_inj = nullptr;   // [640]
+    double2 *d_B = nullptr;           // [n_far][640]
+    // type 2
+    void *d_T2 = nullptr;             // [R+1][Lpad] complex Real
+    void *d_cgrid = nullptr;          // [Lpad][Lpad] Real
+    int2 *d_tgt_base = nullptr;
+    void *d_tgt_wts = nullptr;
+    int32_t *d_ttile_off = nullptr, *d_ttile_tgt = nullptr;
+    double *d_uh = nullptr, *d_ul = nullptr;   // sorted target order
+    // local part
+    int32_t ncell = 1;
+    double cell_h = 2.0;
+    int32_t *d_cell_start = nullptr;  // sources per cell (sorted), size ncell^2 + 1
+    int32_t *d_tgt_cell = nullptr;    // cell of each sorted target
+    SubPanel *d_subs = nullptr;
+    double *d_cheb = nullptr;         // [n_sub][nlev][kChebDeg]
+    int32_t *d_panel_base = nullptr;  // regular panel k -> first sub-panel, and log2 count
+    int32_t *d_panel_l2n = nullptr;
+    int32_t dy_base = 0, n_dy = 0;
+
+    std::string err;
+
+    template <class T>
+    T *alloc(int64_t count);
+    ~Plan();
+};
+
+}  // namespace wfp2d

@@ -1,0 +1,762 @@
+// HIP kernels of the wfp2d per-step pipeline, written for gfx950 (wave64).
+//
+// Step (Sec. 4.3 and Sec. 5):   ingest sigma -> packed type-1 NUFFT of
+//   sigma(t_m) + i sigma(t_{m-LA}) (spread, row FFTs, column FFTs, Hermitian
+//   split into the near and lag rings) -> near-history recurrence per mode ->
+//   far-history SOE recurrence per far mode.
+// Evaluate (eqs. uhtraptrunc, ufhApprox, ul_GL): column and row inverse FFTs
+//   of the combined coefficients -> interpolation at the targets -> local
+//   singular quadrature -> u = u_h + u_l in caller order.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wfp2d_internal.h"
+
+namespace wfp2d {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+template <class R> struct cplx;
+template <> struct cplx<float> { using T = float2; };
+template <> struct cplx<double> { using T = double2; };
+
+template <class C> __device__ __forceinline__ C cmul(C a, C b) { return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <class C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <class C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <class C> __device__ __forceinline__ C cconj(C a) { return C{a.x, -a.y}; }
+__device__ __forceinline__ double2 to_d(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ double2 to_d(double2 a) { return a; }
+template <class C> __device__ __forceinline__ C from_d(double2 a);
+template <> __device__ __forceinline__ float2 from_d<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+template <> __device__ __forceinline__ double2 from_d<double2>(double2 a) { return a; }
+
+template <class R> constexpr int qmax() { return sizeof(R) == 4 ? 8192 : 4096; }
+
+// ---------------------------------------------------------------------------
+// sigma ingest: ring slot <- caller's samples gathered into sorted order
+// ---------------------------------------------------------------------------
+__global__ void k_ingest(const double *__restrict__ in, const int32_t *__restrict__ perm, double *__restrict__ out, int64_t M)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < M) out[j] = in[perm[j]];
+}
+
+// ---------------------------------------------------------------------------
+// Type-1 spreading of c_j = sigma_cur[j] + i sigma_lag[j] onto the band grid.
+// One workgroup owns one kTile x kTile tile: it accumulates, in LDS, every
+// source whose kernel support meets the tile (a precomputed list) and writes
+// the tile with plain coalesced stores, so no global atomics are needed.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_spread(const double *__restrict__ sig_cur, const double *__restrict__ sig_lag,
+                                                const int2 *__restrict__ base, const R *__restrict__ wts,
+                                                const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_src,
+                                                typename cplx<R>::T *__restrict__ grid, int w, int ntx, int Lpad)
+{
+    using C = typename cplx<R>::T;
+    __shared__ R acc_re[kTile * kTile];
+    __shared__ R acc_im[kTile * kTile];
+    const int tile = blockIdx.x, tx = tile % ntx, ty = tile / ntx;
+    const int ox = tx * kTile, oy = ty * kTile;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kTile * kTile; i += blockDim.x) {
+        acc_re[i] = R(0);
+        acc_im[i] = R(0);
+    }
+    __syncthreads();
+    const int beg = tile_off[tile], end = tile_off[tile + 1];
+    const int wave = tid >> 6, lane = tid & 63, nwave = blockDim.x >> 6;
+    const int w2 = w * w;
+    for (int e = beg + wave; e < end; e += nwave) {
+        const int j = tile_src[e];
+        const R cr = (R)sig_cur[j], ci = (R)sig_lag[j];
+        const int2 b = base[j];
+        const R *wj = wts + (size_t)j * 2 * w;
+        for (int q = lane; q < w2; q += 64) {
+            const int a = q % w, bb = q / w;
+            const int gx = b.x + a - ox, gy = b.y + bb - oy;
+            if (gx >= 0 && gx < kTile && gy >= 0 && gy < kTile) {
+                const R k = wj[a] * wj[w + bb];
+                atomicAdd(&acc_re[gy * kTile + gx], cr * k);
+                atomicAdd(&acc_im[gy * kTile + gx], ci * k);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < kTile * kTile; i += blockDim.x) {
+        const int gy = i / kTile, gx = i % kTile;
+        grid[(size_t)(oy + gy) * Lpad + ox + gx] = C{acc_re[i], acc_im[i]};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// In-LDS Stockham FFT of length Q (power of two), radix 4 with a final radix-2
+// stage when log2 Q is odd.  sign = +1 computes sum x[m] e^{+2 pi i k m/Q},
+// sign = -1 the conjugate kernel.  Twiddles come from tw[j] = e^{2 pi i j/nf},
+// nf = P Q.  Returns the buffer that holds the result.
+// ---------------------------------------------------------------------------
+template <class C>
+__device__ __forceinline__ C twid(const C *__restrict__ tw, int idx, int sign)
+{
+    C t = tw[idx];
+    if (sign < 0) t.y = -t.y;
+    return t;
+}
+
+template <class C>
+__device__ C *stockham(C *x, C *y, int Q, int sign, const C *__restrict__ tw, int P)
+{
+    int Ns = 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    while (Ns < Q) {
+        if (Q / Ns >= 4) {
+            const int nq = Q >> 2;
+            const int stride = (Q / (4 * Ns)) * P;
+            for (int j = tid; j < nq; j += nt) {
+                const int k = j % Ns;
+                C v0 = x[j], v1 = x[j + nq], v2 = x[j + 2 * nq], v3 = x[j + 3 * nq];
+                if (Ns > 1) {
+                    v1 = cmul(v1, twid(tw, k * stride, sign));
+                    v2 = cmul(v2, twid(tw, 2 * k * stride, sign));
+                    v3 = cmul(v3, twid(tw, 3 * k * stride, sign));
+                }
+                const C s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = csub(v1, v3);
+                const C wd = sign > 0 ? C{-d13.y, d13.x} : C{d13.y, -d13.x};
+                const int o = (j / Ns) * Ns * 4 + k;
+                y[o] = cadd(s02, s13);
+                y[o + Ns] = cadd(d02, wd);
+                y[o + 2 * Ns] = csub(s02, s13);
+                y[o + 3 * Ns] = csub(d02, wd);
+            }
+            Ns <<= 2;
+        } else {
+            const int nh = Q >> 1;
+            const int stride = (Q / (2 * Ns)) * P;
+            for (int j = tid; j < nh; j += nt) {
+                const int k = j % Ns;
+                C v0 = x[j], v1 = x[j + nh];
+                if (Ns > 1) v1 = cmul(v1, twid(tw, k * stride, sign));
+                const int o = (j / Ns) * Ns * 2 + k;
+                y[o] = cadd(v0, v1);
+                y[o + Ns] = csub(v0, v1);
+            }
+            Ns <<= 1;
+        }
+        __syncthreads();
+        C *t = x;
+        x = y;
+        y = t;
+    }
+    return x;
+}
+
+// map sub-transform output k' of branch s to a signed mode n in [-R, R]; false if unused
+__device__ __forceinline__ bool out_mode(int kp, int s, const Geom &g, int &n)
+{
+    const int k = g.P * kp + s;
+    if (k <= g.R) { n = k; return true; }
+    if (k >= g.nf - g.R) { n = k - g.nf; return true; }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Type-1, first dimension: each band row -> modes n_x in [-R, R] (times the
+// x-direction correction e^{2 pi i n lmin/nf}/psi_hat(n)).  The length-nf
+// transform of a row that is zero outside its first Q entries is split into
+// P length-Q transforms of the twiddled row (nf = P Q).
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_rows1(const typename cplx<R>::T *__restrict__ grid, typename cplx<R>::T *__restrict__ T1,
+                                               const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
+{
+    using C = typename cplx<R>::T;
+    constexpr int QM = qmax<R>();
+    constexpr int NPT = QM / 256;
+    __shared__ C bufA[QM];
+    __shared__ C bufB[QM];
+    const int row = blockIdx.x, tid = threadIdx.x;
+    C xin[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int m = tid + 256 * i;
+        xin[i] = (m < g.Lpad) ? grid[(size_t)row * g.Lpad + m] : C{0, 0};
+    }
+    for (int s = 0; s < g.P; ++s) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int m = tid + 256 * i;
+            if (m < g.Q) bufA[m] = (m < g.Lpad) ? (s == 0 ? xin[i] : cmul(xin[i], tw[(s * m) % g.nf])) : C{0, 0};
+        }
+        __syncthreads();
+        C *res = stockham(bufA, bufB, g.Q, +1, tw, g.P);
+        for (int kp = tid; kp < g.Q; kp += 256) {
+            int n;
+            if (out_mode(kp, s, g, n)) T1[(size_t)row * g.N + n + g.R] = cmul(res[kp], corr[n + g.R]);
+        }
+        __syncthreads();
+    }
+}
+
+// Type-1, second dimension: each column n_x -> F(n_x, n_y) inside the disk.
+template <class R>
+__global__ __launch_bounds__(256) void k_cols1(const typename cplx<R>::T *__restrict__ T1, typename cplx<R>::T *__restrict__ F,
+                                               const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
+{
+    using C = typename cplx<R>::T;
+    constexpr int QM = qmax<R>();
+    constexpr int NPT = QM / 256;
+    __shared__ C bufA[QM];
+    __shared__ C bufB[QM];
+    const int col = blockIdx.x, tid = threadIdx.x;
+    const int nx = col - g.R;
+    C xin[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int m = tid + 256 * i;
+        xin[i] = (m < g.Lpad) ? T1[(size_t)m * g.N + col] : C{0, 0};
+    }
+    for (int s = 0; s < g.P; ++s) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int m = tid + 256 * i;
+            if (m < g.Q) bufA[m] = (m < g.Lpad) ? (s == 0 ? xin[i] : cmul(xin[i], tw[(s * m) % g.nf])) : C{0, 0};
+        }
+        __syncthreads();
+        C *res = stockham(bufA, bufB, g.Q, +1, tw, g.P);
+        for (int kp = tid; kp < g.Q; kp += 256) {
+            int ny;
+            if (out_mode(kp, s, g, ny) && (double)(nx * nx + ny * ny) <= g.Rd2)
+                F[(size_t)col * g.N + ny + g.R] = cmul(res[kp], corr[ny + g.R]);
+        }
+        __syncthreads();
+    }
+}
+
+// Hermitian split of the packed transform: F = S(t_m) + i S(t_{m-LA}).
+template <class R>
+__global__ __launch_bounds__(256) void k_split(const typename cplx<R>::T *__restrict__ F, const ModeChunk *__restrict__ chunks,
+                                               typename cplx<R>::T *__restrict__ cur, typename cplx<R>::T *__restrict__ lag, Geom g)
+{
+    using C = typename cplx<R>::T;
+    const ModeChunk c = chunks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= c.cnt) return;
+    const int nx = c.nx, ny = c.ny0 + t;
+    const C a = F[(size_t)(nx + g.R) * g.N + ny + g.R];
+    const C b = F[(size_t)(-nx + g.R) * g.N + (-ny + g.R)];
+    const R h = R(0.5);
+    cur[c.off + t] = C{h * (a.x + b.x), h * (a.y - b.y)};
+    // (a - conj b) / (2i)
+    lag[c.off + t] = C{h * (a.y + b.y), -h * (a.x - b.x)};
+}
+
+// ---------------------------------------------------------------------------
+// Near history (Sec. 4.3).  With the trapezoid rule on the time grid,
+//   alpha(k, t_m) = dt sum_l sin(k l dt)/k w_l S(t_{m-l}),
+//   w_l = phi(l dt) phi(A+ - l dt)   (eq. alphak),
+// split into the blending edges (W-tap FIRs at delays 1..W-1 and
+// LA+1..LA+W-1) and the interior l in [W, LA] where w_l = 1.  The interior sum
+//   D_m = sum_{l=W}^{LA} sin(k l dt)/k S_{m-l},  C_m = sum cos(k l dt) S_{m-l}
+// obeys the exact two-term rotation of eq. alphakEvolution, forced by the
+// sample entering at delay W-1 and the one leaving at delay LA.  State and
+// coefficients are FP64; ring taps are the plan's precision.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_near(const ModeChunk *__restrict__ chunks, const typename cplx<R>::T *__restrict__ cur,
+                                              const typename cplx<R>::T *__restrict__ lag, double2 *__restrict__ Dst,
+                                              double2 *__restrict__ Cst, const double *__restrict__ phi_in,
+                                              typename cplx<R>::T *__restrict__ atot, int64_t H, int64_t m, Geom g)
+{
+    using C = typename cplx<R>::T;
+    const ModeChunk c = chunks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= c.cnt) return;
+    const int64_t pk = c.off + t;
+    const int nx = c.nx, ny = c.ny0 + t;
+    const double key = (double)(nx * nx + ny * ny);
+    if (key * g.dk * g.dk > g.K * g.K) {  // far-only mode beyond the near cutoff
+        atot[pk] = C{0, 0};
+        return;
+    }
+    const double kap = g.dk * sqrt(key);
+    const int W = g.W, LA = g.LA;
+    double s1, c1;
+    sincos(kap * g.dt, &s1, &c1);
+    const double2 E = make_double2(c1, s1);
+    const double inv = kap > 0.0 ? 1.0 / kap : 0.0;
+    double2 D = Dst[pk], Cs = Cst[pk];
+    double2 al = D;
+    double2 Pw = E;
+    double fs = 0.0, fc = 1.0;
+    double2 Sin = make_double2(0.0, 0.0);
+    for (int l = 1; l < W; ++l) {
+        const double sk = kap > 0.0 ? Pw.y * inv : l * g.dt;
+        const int64_t slot = ((m - l) % W + W) % W;
+        const double2 S = to_d(cur[slot * H + pk]);
+        const double cf = sk * phi_in[l];
+        al.x += cf * S.x;
+        al.y += cf * S.y;
+        if (l == W - 1) {
+            fs = sk;
+            fc = Pw.x;
+            Sin = S;
+        }
+        Pw = cmul(Pw, E);
+    }
+    double sL, cL;
+    sincos(kap * ((double)LA * g.dt), &sL, &cL);
+    double2 Qw = cmul(make_double2(cL, sL), E);
+    for (int l = LA + 1; l < LA + W; ++l) {
+        const double sk = kap > 0.0 ? Qw.y * inv : l * g.dt;
+        const int64_t slot = ((m - l) % W + W) % W;
+        const double2 S = to_d(lag[slot * H + pk]);
+        const double cf = sk * phi_in[LA + W - l];
+        al.x += cf * S.x;
+        al.y += cf * S.y;
+        Qw = cmul(Qw, E);
+    }
+    const double2 SLA = to_d(lag[(((m - LA) % W + W) % W) * H + pk]);
+    const double scale = g.dt * (g.dk / (2.0 * M_PI)) * (g.dk / (2.0 * M_PI));
+    atot[pk] = from_d<C>(make_double2(al.x * scale, al.y * scale));
+    // advance the interior sums by one step
+    const double gs = kap > 0.0 ? sL * inv : LA * g.dt, gc = cL;
+    const double2 Dt = make_double2(D.x + fs * Sin.x - gs * SLA.x, D.y + fs * Sin.y - gs * SLA.y);
+    const double2 Ct = make_double2(Cs.x + fc * Sin.x - gc * SLA.x, Cs.y + fc * Sin.y - gc * SLA.y);
+    const double so = kap > 0.0 ? s1 * inv : g.dt;
+    const double ks = kap * s1;
+    Dst[pk] = make_double2(c1 * Dt.x + so * Ct.x, c1 * Dt.y + so * Ct.y);
+    Cst[pk] = make_double2(c1 * Ct.x - ks * Dt.x, c1 * Ct.y - ks * Dt.y);
+}
+
+// ---------------------------------------------------------------------------
+// Far history (Sec. 5): alpha_F = sum_l H_l(kappa) beta_l with, by the
+// trapezoid rule on the time grid (scaled by e^{A lambda}, eq. beta0),
+//   beta_l(t_m) = B_l(t_m) + sum_{i<W-1} (window taps),
+//   B_l(t_{m+1}) = e^{-lambda_l dt} [B_l(t_m) + dt e^{-lambda_l((LA+W-1)dt - A)} S_{m-LA-W+1}],
+// the one-term recurrence of eq. betaEvolution.  The window taps are folded
+// with H into chi.  One wavefront per far mode; FP64.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_far(const int32_t *__restrict__ far_pk, const int32_t *__restrict__ far_cls,
+                                             const double *__restrict__ Htab, const double *__restrict__ chi,
+                                             const double *__restrict__ dec, const double *__restrict__ inj,
+                                             double2 *__restrict__ B, const typename cplx<R>::T *__restrict__ lag,
+                                             typename cplx<R>::T *__restrict__ atot, int64_t n_far, int64_t H, int64_t m, Geom g)
+{
+    using C = typename cplx<R>::T;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t f = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (f >= n_far) return;
+    const int W = g.W, LA = g.LA;
+    const int64_t pk = far_pk[f];
+    const int cls = far_cls[f];
+    const double2 Snew = to_d(lag[(((m - LA - W + 1) % W + W) % W) * H + pk]);
+    double ax = 0.0, ay = 0.0;
+    double2 *Bf = B + f * kNsoe;
+    const double *Hc = Htab + (size_t)cls * kNsoe;
+    for (int l = lane; l < kNsoe; l += 64) {
+        const double2 b = Bf[l];
+        const double h = Hc[l];
+        ax += h * b.x;
+        ay += h * b.y;
+        const double d = dec[l], in = inj[l];
+        Bf[l] = make_double2(d * (b.x + in * Snew.x), d * (b.y + in * Snew.y));
+    }
+    for (int i = lane; i < W - 1; i += 64) {
+        const int64_t slot = ((m - (LA + 1 + i)) % W + W) % W;
+        const double2 S = to_d(lag[slot * H + pk]);
+        const double x = chi[(size_t)cls * (W - 1) + i];
+        ax += x * S.x;
+        ay += x * S.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ax += __shfl_down(ax, off, 64);
+        ay += __shfl_down(ay, off, 64);
+    }
+    if (lane == 0) {
+        const double scale = (g.dk / (2.0 * M_PI)) * (g.dk / (2.0 * M_PI));
+        const double2 a0 = to_d(atot[pk]);
+        atot[pk] = from_d<C>(make_double2(a0.x + scale * ax, a0.y + scale * ay));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Type-2, first dimension: for each column n_x >= 0 of the packed half disk,
+// b(n) = (2 or 1) a(n) conj(corr_x) conj(corr_y) -> c(n_x, m_y) for band rows.
+// u = Re sum_n b(n) e^{-i n.x}: Hermitian data is summed over one half plane
+// with doubled weights (the origin counted once).
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_cols2(const typename cplx<R>::T *__restrict__ atot, const int32_t *__restrict__ col_off,
+                                               const int32_t *__restrict__ col_ny0, typename cplx<R>::T *__restrict__ T2,
+                                               const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
+{
+    using C = typename cplx<R>::T;
+    constexpr int QM = qmax<R>();
+    constexpr int NPT = QM / 256;
+    __shared__ C bufA[QM];
+    __shared__ C bufB[QM];
+    const int nx = blockIdx.x, tid = threadIdx.x;
+    const int off = col_off[nx], cnt = col_off[nx + 1] - off, ny0 = col_ny0[nx];
+    const C cx = cconj(corr[nx + g.R]);
+    C acc[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) acc[i] = C{0, 0};
+    for (int s = 0; s < g.P; ++s) {
+        for (int kp = tid; kp < g.Q; kp += 256) {
+            int ny;
+            C v{0, 0};
+            if (out_mode(kp, s, g, ny) && ny >= ny0 && ny < ny0 + cnt) {
+                const R fac = (nx > 0 || ny > 0) ? R(2) : R(1);
+                const C a = atot[off + (ny - ny0)];
+                v = cmul(cmul(a, cx), cconj(corr[ny + g.R]));
+                v.x *= fac;
+                v.y *= fac;
+            }
+            bufA[kp] = v;
+        }
+        __syncthreads();
+        C *res = stockham(bufA, bufB, g.Q, -1, tw, g.P);
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int m = tid + 256 * i;
+            if (m < g.Lpad) {
+                C r = res[m];
+                if (s > 0) r = cmul(r, cconj(tw[(s * m) % g.nf]));
+                acc[i] = cadd(acc[i], r);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int m = tid + 256 * i;
+        if (m < g.Lpad) T2[(size_t)nx * g.Lpad + m] = acc[i];
+    }
+}
+
+// Type-2, second dimension: each band row m_y, modes n_x in [0, R] -> real grid.
+template <class R>
+__global__ __launch_bounds__(256) void k_rows2(const typename cplx<R>::T *__restrict__ T2, R *__restrict__ cgrid,
+                                               const typename cplx<R>::T *__restrict__ tw, Geom g)
+{
+    using C = typename cplx<R>::T;
+    constexpr int QM = qmax<R>();
+    constexpr int NPT = QM / 256;
+    __shared__ C bufA[QM];
+    __shared__ C bufB[QM];
+    const int row = blockIdx.x, tid = threadIdx.x;
+    C acc[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) acc[i] = C{0, 0};
+    for (int s = 0; s < g.P; ++s) {
+        for (int kp = tid; kp < g.Q; kp += 256) {
+            const int k = g.P * kp + s;
+            bufA[kp] = (k <= g.R) ? T2[(size_t)k * g.Lpad + row] : C{0, 0};
+        }
+        __syncthreads();
+        C *res = stockham(bufA, bufB, g.Q, -1, tw, g.P);
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int m = tid + 256 * i;
+            if (m < g.Lpad) {
+                C r = res[m];
+                if (s > 0) r = cmul(r, cconj(tw[(s * m) % g.nf]));
+                acc[i] = cadd(acc[i], r);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int m = tid + 256 * i;
+        if (m < g.Lpad) cgrid[(size_t)row * g.Lpad + m] = acc[i].x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Type-2 interpolation: one workgroup per tile stages the tile's grid region
+// (kTile + w - 1)^2 in LDS; each target of the tile sums w^2 products.
+// ---------------------------------------------------------------------------
+constexpr int kWmax = 16;
+template <class R>
+__global__ __launch_bounds__(256) void k_interp(const R *__restrict__ cgrid, const int2 *__restrict__ base, const R *__restrict__ wts,
+                                                const int32_t *__restrict__ toff, const int32_t *__restrict__ tlist,
+                                                double *__restrict__ uh, int w, int ntx, int Lpad)
+{
+    constexpr int RW = kTile + kWmax - 1;
+    __shared__ R reg[RW * RW];
+    const int tile = blockIdx.x, tx = tile % ntx, ty = tile / ntx;
+    const int ox = tx * kTile, oy = ty * kTile;
+    const int rw = kTile + w - 1;
+    for (int i = threadIdx.x; i < rw * rw; i += blockDim.x) {
+        const int yy = i / rw, xx = i % rw;
+        const int gy = oy + yy, gx = ox + xx;
+        reg[yy * RW + xx] = (gy < Lpad && gx < Lpad) ? cgrid[(size_t)gy * Lpad + gx] : R(0);
+    }
+    __syncthreads();
+    const int beg = toff[tile], end = toff[tile + 1];
+    for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        const int i = tlist[e];
+        const int2 b = base[i];
+        const R *wi = wts + (size_t)i * 2 * w;
+        const int bx = b.x - ox, by = b.y - oy;
+        double sum = 0.0;
+        for (int bb = 0; bb < w; ++bb) {
+            double row = 0.0;
+            for (int a = 0; a < w; ++a) row += (double)wi[a] * (double)reg[(by + bb) * RW + bx + a];
+            sum += row * (double)wi[w + bb];
+        }
+        uh[i] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Local part (Sec. 6, eq. ul_GL with eq. sigInterp): for each target, the
+// sources within delta in the 3x3 neighbouring cells; eta_d(r) from the
+// Chebyshev sub-panel tables; u_l = (1/2pi) sum_j sum_d eta_d(r) sigma_j(t_{m-d}).
+// ---------------------------------------------------------------------------
+struct LocalArgs {
+    const double2 *txy, *sxy;
+    const int32_t *tcell, *cell_start;
+    const SubPanel *subs;
+    const double *cheb;
+    const int32_t *pbase, *pl2n;
+    const double *sig;
+    double *ul;
+    int ncell, dy_base, n_dy;
+    double delta;
+};
+
+__device__ __forceinline__ double cheb_eval(const double *__restrict__ c, double x)
+{
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = kChebDeg - 1; k >= 1; --k) {
+        const double b0 = fma(2.0 * x, b1, c[k] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(x, b1, c[0] - b2);
+}
+
+__global__ __launch_bounds__(256) void k_local(LocalArgs A, int64_t m, Geom g)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Nx) return;
+    const double2 x = A.txy[i];
+    const int c = A.tcell[i], cx = c % A.ncell, cy = c / A.ncell;
+    const double d2 = A.delta * A.delta;
+    double acc = 0.0;
+    for (int yy = max(0, cy - 1); yy <= min(A.ncell - 1, cy + 1); ++yy)
+        for (int xx = max(0, cx - 1); xx <= min(A.ncell - 1, cx + 1); ++xx) {
+            const int cc = yy * A.ncell + xx;
+            for (int j = A.cell_start[cc]; j < A.cell_start[cc + 1]; ++j) {
+                const double2 y = A.sxy[j];
+                const double dx = x.x - y.x, dy = x.y - y.y, r2 = dx * dx + dy * dy;
+                if (!(r2 > 0.0 && r2 < d2)) continue;
+                const double r = sqrt(r2);
+                const double rr = r / g.dt;
+                int sub;
+                if (rr >= 0.5) {
+                    const int k = min((int)rr, g.W - 1);
+                    const double lo = k == 0 ? 0.5 : (double)k, wd = k == 0 ? 0.5 : 1.0;
+                    const int ns = 1 << A.pl2n[k];
+                    sub = A.pbase[k] + min((int)((rr - lo) / wd * ns), ns - 1);
+                } else {
+                    int e;
+                    frexp(rr, &e);
+                    int idx = min(-e, A.n_dy);
+                    sub = A.dy_base + idx - 1;
+                }
+                const SubPanel sp = A.subs[sub];
+                double xc;
+                if (sp.c > 0.0) {
+                    const double u = sqrt(fmax(0.0, sp.c - r));
+                    xc = (2.0 * u - sp.ua - sp.ub) / (sp.ua - sp.ub);
+                } else {
+                    xc = (2.0 * r - sp.ra - sp.rb) / (sp.rb - sp.ra);
+                }
+                xc = fmin(1.0, fmax(-1.0, xc));
+                const double *cf = A.cheb + (size_t)sub * g.nlev * kChebDeg;
+                for (int d = 0; d < g.nlev; ++d) {
+                    const int64_t lvl = m - (g.lev_min + d);
+                    const int64_t slot = ((lvl % g.sig_depth) + g.sig_depth) % g.sig_depth;
+                    acc = fma(cheb_eval(cf + d * kChebDeg, xc), A.sig[slot * g.M + j], acc);
+                }
+            }
+        }
+    A.ul[i] = acc * (0.5 / M_PI);
+}
+
+// u (caller order) = u_h + u_l, or zeros before the first reported step
+__global__ void k_combine(const double *__restrict__ uh, const double *__restrict__ ul, const int32_t *__restrict__ rank,
+                          double *__restrict__ u, int64_t Nx, int zero)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nx) return;
+    if (zero) {
+        u[i] = 0.0;
+        return;
+    }
+    const int s = rank[i];
+    u[i] = uh[s] + ul[s];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_ingest(Plan &p, const double *sigma_in, int64_t slot)
+{
+    hipLaunchKernelGGL(k_ingest, dim3(nblk(p.M, 256)), dim3(256), 0, p.stream, sigma_in, p.d_src_perm, p.d_sig + slot * p.M, p.M);
+    return hipGetLastError();
+}
+
+hipError_t launch_spread(Plan &p, int64_t slot_cur, int64_t slot_lag)
+{
+    const Geom &g = p.g;
+    const double *sc = p.d_sig + slot_cur * p.M, *sl = p.d_sig + slot_lag * p.M;
+    const unsigned nt = (unsigned)(g.ntx * g.ntx);
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_spread<float>, dim3(nt), dim3(256), 0, p.stream, sc, sl, p.d_src_base, (const float *)p.d_src_wts,
+                           p.d_tile_off, p.d_tile_src, (float2 *)p.d_grid, g.w, g.ntx, g.Lpad);
+    else
+        hipLaunchKernelGGL(k_spread<double>, dim3(nt), dim3(256), 0, p.stream, sc, sl, p.d_src_base, (const double *)p.d_src_wts,
+                           p.d_tile_off, p.d_tile_src, (double2 *)p.d_grid, g.w, g.ntx, g.Lpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_rows1(Plan &p)
+{
+    const Geom &g = p.g;
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_rows1<float>, dim3(g.Lpad), dim3(256), 0, p.stream, (const float2 *)p.d_grid, (float2 *)p.d_T1,
+                           (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+    else
+        hipLaunchKernelGGL(k_rows1<double>, dim3(g.Lpad), dim3(256), 0, p.stream, (const double2 *)p.d_grid, (double2 *)p.d_T1,
+                           (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_cols1(Plan &p)
+{
+    const Geom &g = p.g;
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_cols1<float>, dim3(g.N), dim3(256), 0, p.stream, (const float2 *)p.d_T1, (float2 *)p.d_F,
+                           (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+    else
+        hipLaunchKernelGGL(k_cols1<double>, dim3(g.N), dim3(256), 0, p.stream, (const double2 *)p.d_T1, (double2 *)p.d_F,
+                           (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(Plan &p, int64_t ring_cur, int64_t ring_lag)
+{
+    const Geom &g = p.g;
+    const int64_t H = p.n_modes;
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_split<float>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, (const float2 *)p.d_F, p.d_chunks,
+                           (float2 *)p.d_ring_cur + ring_cur * H, (float2 *)p.d_ring_lag + ring_lag * H, g);
+    else
+        hipLaunchKernelGGL(k_split<double>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, (const double2 *)p.d_F, p.d_chunks,
+                           (double2 *)p.d_ring_cur + ring_cur * H, (double2 *)p.d_ring_lag + ring_lag * H, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_near(Plan &p, int64_t m)
+{
+    const Geom &g = p.g;
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_near<float>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, p.d_chunks, (const float2 *)p.d_ring_cur,
+                           (const float2 *)p.d_ring_lag, p.d_D, p.d_C, p.d_phi_in, (float2 *)p.d_atot, p.n_modes, m, g);
+    else
+        hipLaunchKernelGGL(k_near<double>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, p.d_chunks, (const double2 *)p.d_ring_cur,
+                           (const double2 *)p.d_ring_lag, p.d_D, p.d_C, p.d_phi_in, (double2 *)p.d_atot, p.n_modes, m, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_far(Plan &p, int64_t m)
+{
+    const Geom &g = p.g;
+    if (p.n_far == 0) return hipSuccess;
+    const unsigned nb = nblk(p.n_far, 4);
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_far<float>, dim3(nb), dim3(256), 0, p.stream, p.d_far_pk, p.d_far_cls, p.d_H, p.d_chi, p.d_dec, p.d_inj,
+                           p.d_B, (const float2 *)p.d_ring_lag, (float2 *)p.d_atot, p.n_far, p.n_modes, m, g);
+    else
+        hipLaunchKernelGGL(k_far<double>, dim3(nb), dim3(256), 0, p.stream, p.d_far_pk, p.d_far_cls, p.d_H, p.d_chi, p.d_dec, p.d_inj,
+                           p.d_B, (const double2 *)p.d_ring_lag, (double2 *)p.d_atot, p.n_far, p.n_modes, m, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_cols2(Plan &p)
+{
+    const Geom &g = p.g;
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_cols2<float>, dim3(g.R + 1), dim3(256), 0, p.stream, (const float2 *)p.d_atot, p.d_col_off, p.d_col_ny0,
+                           (float2 *)p.d_T2, (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+    else
+        hipLaunchKernelGGL(k_cols2<double>, dim3(g.R + 1), dim3(256), 0, p.stream, (const double2 *)p.d_atot, p.d_col_off, p.d_col_ny0,
+                           (double2 *)p.d_T2, (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_rows2(Plan &p)
+{
+    const Geom &g = p.g;
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_rows2<float>, dim3(g.Lpad), dim3(256), 0, p.stream, (const float2 *)p.d_T2, (float *)p.d_cgrid,
+                           (const float2 *)p.d_tw, g);
+    else
+        hipLaunchKernelGGL(k_rows2<double>, dim3(g.Lpad), dim3(256), 0, p.stream, (const double2 *)p.d_T2, (double *)p.d_cgrid,
+                           (const double2 *)p.d_tw, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(Plan &p)
+{
+    const Geom &g = p.g;
+    const unsigned nt = (unsigned)(g.ntx * g.ntx);
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_interp<float>, dim3(nt), dim3(256), 0, p.stream, (const float *)p.d_cgrid, p.d_tgt_base,
+                           (const float *)p.d_tgt_wts, p.d_ttile_off, p.d_ttile_tgt, p.d_uh, g.w, g.ntx, g.Lpad);
+    else
+        hipLaunchKernelGGL(k_interp<double>, dim3(nt), dim3(256), 0, p.stream, (const double *)p.d_cgrid, p.d_tgt_base,
+                           (const double *)p.d_tgt_wts, p.d_ttile_off, p.d_ttile_tgt, p.d_uh, g.w, g.ntx, g.Lpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_local(Plan &p, int64_t m)
+{
+    LocalArgs A;
+    A.txy = p.d_tgt_xy;
+    A.sxy = p.d_src_xy;
+    A.tcell = p.d_tgt_cell;
+    A.cell_start = p.d_cell_start;
+    A.subs = p.d_subs;
+    A.cheb = p.d_cheb;
+    A.pbase = p.d_panel_base;
+    A.pl2n = p.d_panel_l2n;
+    A.sig = p.d_sig;
+    A.ul = p.d_ul;
+    A.ncell = p.ncell;
+    A.dy_base = p.dy_base;
+    A.n_dy = p.n_dy;
+    A.delta = p.delta;
+    hipLaunchKernelGGL(k_local, dim3(nblk(p.Nx, 256)), dim3(256), 0, p.stream, A, m, p.g);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(Plan &p, double *u_out, int zero)
+{
+    hipLaunchKernelGGL(k_combine, dim3(nblk(p.Nx, 256)), dim3(256), 0, p.stream, p.d_uh, p.d_ul, p.d_tgt_rank, u_out, p.Nx, zero);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(Plan &, void *, int64_t) { return hipSuccess; }
+
+}  // namespace wfp2d

@@ -1,0 +1,36 @@
+"""The C-ABI library loads and exports every symbol its header declares (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+pa = pytest.importorskip("paper_2604_07170_amd")
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pa.load_library()
+    decls = re.findall(r"\b(wfp2d_[a-z_0-9]+)\s*\(", open(pa.HEADER_PATH).read())
+    assert len(set(decls)) >= 9
+    for name in set(decls):
+        assert hasattr(lib, name), name
+
+
+def test_errors_are_status_codes_without_a_device():
+    lib = pa.load_library()
+    plan = ctypes.c_void_p()
+    xy = (ctypes.c_double * 2)(0.0, 0.0)
+    # bad arguments are rejected before any device call
+    assert lib.wfp2d_init(ctypes.byref(plan), 0, xy, 1, xy, 0.1, 16, 1e-7, None) == -1
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, -0.1, 16, 1e-7, None) == -1
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.1, 16, 0.5, None) == -1
+    far = (ctypes.c_double * 2)(1.5, 0.0)
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, far, 1, xy, 0.01, 24, 1e-7, None) == -2
+    # W too small for the tolerance: pi - 2b/W <= 0 (eq. dt)
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.01, 8, 1e-7, None) == -3
+    assert plan.value is None
+    assert b"pi - 2b/W" in lib.wfp2d_last_error(None)
+    assert lib.wfp2d_step(None, None) == -6
+    assert lib.wfp2d_destroy(None) == 0
+    with pytest.raises(pa.Wfp2dError):
+        pa.host_eval(99, [], 1)

@@ -1,0 +1,142 @@
+"""CPU pins of the library's host-side precomputation (no GPU needed).
+
+* derived parameters against the numbers printed in Sec. 5.2;
+* the sum-of-exponentials rule of Sec. 2.3 against the closed form 1/sqrt(t^2-r^2);
+* the Hankel coefficients of eq. H against Table 1, and their kappa = 0 limit
+  against a radial integral done independently with scipy;
+* the local-part weights: the Chebyshev tables against direct quadrature, and
+  the direct quadrature against closed forms (polynomial sigma is integrated
+  exactly; phi = 0 gives acosh);
+* the blending function against its defining integral.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+pa = pytest.importorskip("paper_2604_07170_amd")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read(name):
+    rows = []
+    for line in open(os.path.join(GOLD, name)):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append(line.split())
+    return rows
+
+
+def test_params_reproduce_sec52():
+    g = {r[0]: (float(r[1]), float(r[2])) for r in _read("params_sec52.txt")}
+    P = pa.derive_params(g["dt"][0], int(g["W"][0]), g["tol"][0])
+    assert P["K"] == pytest.approx(g["K"][0], abs=g["K"][1])
+    assert P["dk"] == pytest.approx(g["dk"][0], abs=g["dk"][1])
+    assert P["N"] == int(g["N"][0])
+    assert P["delta"] == pytest.approx(g["delta"][0], abs=g["delta"][1])
+    # eq. dt holds with the paper's margin: K0 + 2b/delta <= K with K0 = 983 (Sec. 5.2)
+    assert 983 + 2 * P["b"] / P["delta"] <= P["K"]
+    # the lagged sample lies on the time grid: (A+ - delta)/dt is an integer
+    assert (P["Aplus"] - P["delta"]) / g["dt"][0] == pytest.approx(P["LA"], abs=1e-6)
+    assert P["a"] >= 1.0 and P["A"] == pytest.approx(2 * math.sqrt(2) + 1)
+
+
+def test_soe_reproduces_inverse_sqrt():
+    v = pa.host_eval(2, [], 1280)
+    lam, q = v[:640], v[640:]
+    P = pa.derive_params(8 / 7150, 16, 1e-7)
+    r = np.linspace(0, P["A"], 41)
+    t = np.concatenate([P["Aplus"] - P["delta"] + np.linspace(0, 1, 11), np.geomspace(6, 3e4, 30)])
+    R, T = np.meshgrid(r, t)
+    approx = np.einsum("l,lij->ij", q, special.i0e(np.multiply.outer(lam, R)) * np.exp(-np.multiply.outer(lam, T - R)))
+    exact = 1 / np.sqrt(T ** 2 - R ** 2)
+    assert np.max(np.abs(approx - exact) / exact) < 1e-13
+    assert lam.size == 640 and np.all(q > 0)
+
+
+def test_hankel_matches_table1():
+    for D, Kf, ref in _read("table1_kf.txt"):
+        D, Kf, ref = float(D), float(Kf), float(ref)
+        A = 2 * math.sqrt(2) + D
+        H = pa.host_eval(3, [A, D, 30.0, Kf], 640)
+        assert ref / 3.0 < np.abs(H).max() < ref * 3.0, (D, Kf, np.abs(H).max(), ref)
+
+
+def test_hankel_at_zero_wavenumber():
+    # kappa = 0: J0 = 1, so H_l = q_l e^{-A lam_l} int_0^A I0(lam_l r) phi_D(A-r) r dr
+    A, D, bD = 2 * math.sqrt(2) + 1, 1.0, 30.0
+    H = pa.host_eval(3, [A, D, bD, 0.0], 640)
+    v = pa.host_eval(2, [], 1280)
+    lam, q = v[:640], v[640:]
+    phi = lambda s: pa.host_eval(6, [D, bD, s], 2)[0]
+    for l in [0, 100, 300, 500, 639]:
+        f = lambda r: special.i0e(lam[l] * r) * math.exp(-lam[l] * (A - r)) * phi(A - r) * r
+        val = integrate.quad(f, 0, A - D, limit=200, epsabs=0, epsrel=1e-13)[0] + \
+            integrate.quad(f, A - D, A, limit=200, epsabs=0, epsrel=1e-13)[0]
+        assert H[l] == pytest.approx(q[l] * val, rel=1e-10, abs=1e-300)
+
+
+def test_blend_matches_definition():
+    delta, b = 0.3, math.log(1e7)
+    t = np.array([0.0, 0.01, 0.1, 0.15, 0.2, 0.29, 0.3, 0.5])
+    out = pa.host_eval(6, [delta, b, *t], 2 * t.size).reshape(-1, 2)
+    dphi = lambda s: b / (delta * math.sinh(b)) * special.i0(b * math.sqrt(max(0.0, 1 - (2 * s / delta - 1) ** 2)))
+    for i, ti in enumerate(t):
+        ref = integrate.quad(dphi, 0, min(ti, delta), epsabs=1e-16, epsrel=1e-14)[0] if ti > 0 else 0.0
+        assert out[i, 0] == pytest.approx(ref, abs=2e-15)
+        if 0 <= ti <= delta:
+            assert out[i, 1] == pytest.approx(dphi(ti), abs=1e-13 * dphi(delta / 2))
+
+
+LOCAL = dict(dt=0.05, W=8, p=6, look=-1, tol=1e-7)
+
+
+def _eta(what, r, dt, W, p, look, tol):
+    nlev = W + p - 1 if look < 0 else None
+    r = np.atleast_1d(r)
+    v = pa.host_eval(what, [dt, W, p, look, tol, *r], 100 * r.size)
+    return v.reshape(r.size, -1)
+
+
+def test_local_weights_integrate_polynomials_exactly():
+    # sigma(t) = (t_m - t)^k on the grid (delay^k), k < p: the interpolant is exact,
+    # so sum_d eta_d(r) (d dt)^k = int_r^delta tau^k [1 - phi(tau)] / sqrt(tau^2 - r^2) dtau
+    dt, W, p, look, tol = LOCAL.values()
+    delta, b = W * dt, math.log(1 / tol)
+    phi = lambda s: pa.host_eval(6, [delta, b, s], 2)[0]
+    for r in [1e-6, 0.013, 0.05, 0.137, 0.35]:
+        e = _eta(4, r, dt, W, p, look, tol)[0]
+        d = np.arange(e.size) - ((p + 1) // 2 - 1)
+        for k in range(p):
+            lhs = np.sum(e * (d * dt) ** k)
+            f = lambda v: (r * math.cosh(v)) ** k * (1 - phi(r * math.cosh(v)))
+            rhs = integrate.quad(f, 0, math.acosh(delta / r), limit=400, epsabs=1e-15, epsrel=1e-12)[0]
+            assert lhs == pytest.approx(rhs, rel=1e-9, abs=1e-13 * max(1, abs(rhs))), (r, k)
+
+
+def test_local_weights_without_window_give_acosh():
+    # with tol -> the blend collapses to ~0 weight of phi only near delta; use sum_d eta_d for
+    # sigma = 1: int_r^delta [1-phi]/sqrt(tau^2-r^2) <= acosh(delta/r), and -> acosh for r near delta
+    dt, W, p, look, tol = LOCAL.values()
+    for r in [1e-4, 0.01, 0.2]:
+        e = _eta(4, r, dt, W, p, look, tol)[0]
+        assert 0 < e.sum() < math.acosh(W * dt / r)
+
+
+@pytest.mark.parametrize("dt,W,p", [(0.05, 8, 6), (0.05, 24, 20), (8 / 7150, 16, 20)])
+def test_local_tables_match_direct_quadrature(dt, W, p):
+    rng = np.random.default_rng(5)
+    delta = W * dt
+    r = np.concatenate([rng.uniform(0, 1, 40) * delta, dt * np.geomspace(1e-9, 0.5, 12),
+                        dt * np.arange(1, W) - 1e-12 * dt, dt * np.arange(1, W) + 1e-12 * dt])
+    r = r[(r > 0) & (r < delta)]
+    r = np.concatenate([r, (np.arange(W)[:, None] + np.linspace(0.02, 0.98, 9)[None, :]).ravel() * dt])
+    direct = _eta(4, r, dt, W, p, -1, 1e-7)
+    table = _eta(5, r, dt, W, p, -1, 1e-7)
+    # error relative to the size of the weights on the same time-step panel of r
+    panel = np.minimum((r / dt).astype(int), W - 1)
+    mag = np.abs(direct).max(axis=1)
+    scale = np.array([mag[panel == k].max() for k in panel])[:, None]
+    assert np.max(np.abs(table - direct) / scale) < 1e-11
