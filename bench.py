@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of the per-step TK-WFP update on one MI355X (source x time-steps per second).
+
+A "step" is one pass of the whole hot path over one time sample: ingest of
+sigma(t_n), packed type-1 NUFFT, near- and far-history recurrences of every
+Fourier mode, type-2 NUFFT and the local singular quadrature at every target
+(``wfp2d_step`` + ``wfp2d_evaluate``).  Inputs are seeded synthetic closed-form
+signatures; the samples of the timed steps are generated into HBM before the
+timed region starts.
+
+Default workload: M = 10^6 random sources = targets in a 300 x 300-wavelength
+square, eps = 1e-7, W = 16, p = 20, dt = 8/7150, timed over steps 5801..6000
+(after the far history has become active at step LA = 4300).
+
+Prints one JSON line (rank 0, one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
+PEAK_FP64_TFLOPS = 78.6        # vector FP64
+PEAK_FP32_TFLOPS = 157.3       # vector FP32
+
+
+def stage_costs(info: dict) -> dict:
+    """Algorithmic work of one launch of each stage: (bound, amount, unit).
+
+    HBM-bound stages count the bytes a launch must move at least once
+    (reads + writes of its inputs, state and outputs); the local part counts
+    FP64 flops (table evaluation plus contraction per source-target pair).
+    """
+    c = 4 if info["precision"] == 1 else 8          # bytes per real in the grid/FFT/ring precision
+    H, W = info["n_modes"], info["W"]
+    Lp, N, R = info["band"], 2 * info["R"] + 1, info["R"]
+    M, Nx, w = info["M"], info["Nx"], info["nufft_w"]
+    nfar, nlev = info["n_far"], info["n_levels"]
+    cost = {
+        "ingest": ("hbm", M * (8 + 4 + 8)),
+        "spread": ("hbm", M * (2 * 8 + 8 + 2 * w * c) + Lp * Lp * 2 * c),
+        "fft_rows1": ("hbm", Lp * Lp * 2 * c + Lp * N * 2 * c),
+        "fft_cols1": ("hbm", Lp * N * 2 * c + 2 * H * 2 * c),
+        "split": ("hbm", 2 * H * 2 * c + 2 * H * 2 * c),
+        # state D, C read+write (FP64 complex), 2W-1 ring taps, combined coefficient out
+        "near": ("hbm", H * (4 * 16 + (2 * W - 1) * 2 * c + 2 * c)),
+        "far": ("hbm", nfar * (640 * (16 + 16 + 8) + W * 2 * c + 2 * 2 * c)),
+        "fft_cols2": ("hbm", H * 2 * c + (R + 1) * Lp * 2 * c),
+        "fft_rows2": ("hbm", (R + 1) * Lp * 2 * c + Lp * Lp * c),
+        "interp": ("hbm", Lp * Lp * c + Nx * (8 + 2 * w * c + 8)),
+        # Clenshaw of degree 16 per level (2 flops x 16) + contraction (2 flops) per level and pair
+        "local": ("alu", info["n_local_pairs"] * nlev * (2 * info["cheb_degree"] + 2)),
+        "combine": ("hbm", Nx * (8 + 8 + 4 + 8)),
+    }
+    return cost
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5800)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--cpu-sample-targets", type=int, default=1,
+                    help="targets of the CPU oracle sample (at the last timed step)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding of the "
+                                   "method is described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2604_07170_amd as pa
+    from wfp_workloads import config
+
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = config(args.config)
+    t0 = time.time()
+    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=args.precision, interp_order=w.p,
+                    max_steps=args.warmup + args.steps + 32)
+    info = plan.info()
+    L = info["lookahead"]
+    log(f"[bench] {w.name}: plan ready in {time.time() - t0:.1f}s  modes={info['n_modes']} nf={info['nf']} "
+        f"band={info['band']} pairs={info['n_local_pairs']} lookahead={L} HBM={info['bytes_device'] / 2**30:.1f}GiB")
+    params = w.torch_params(dev)
+    u = torch.empty(w.Nx, dtype=torch.float64, device=dev)
+
+    # ---- warm-up: the full pipeline, so the timed window starts at step warmup+1 ----
+    t0 = time.time()
+    nw = args.warmup
+    for n in range(1, nw + 1):
+        plan.step(w.sigma_torch(n * w.dt, dev, params))
+        if n > nw - 3:
+            plan.evaluate(u)
+        if n % 500 == 0:
+            torch.cuda.synchronize()
+            log(f"[bench] warm-up step {n}/{nw} ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+
+    # ---- inputs of the timed steps, resident in HBM before timing ----
+    K = args.steps
+    sig = torch.empty((K, w.M), dtype=torch.float64, device=dev)
+    for k in range(K):
+        sig[k] = w.sigma_torch((nw + 1 + k) * w.dt, dev, params)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K whole steps, HIP events on the plan's stream ----
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(K):
+        plan.step(sig[k])
+        plan.evaluate(u)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    elapsed_ms = ev0.elapsed_time(ev1)
+    stages = plan.get_timing()
+    plan.set_timing(False)
+    step_reported = plan.info()["step_reported"]
+    ms_per_step = elapsed_ms / K
+    value = w.M * K / (elapsed_ms / 1e3)
+    log(f"[bench] timed {K} steps: {elapsed_ms:.1f} ms (wall {wall * 1e3:.1f} ms), {ms_per_step:.3f} ms/step")
+
+    # ---- roofline of the dominant kernel ----
+    costs = stage_costs(info)
+    per_stage = {}
+    for s, (ms, n) in stages.items():
+        if n == 0:
+            continue
+        bound, amt = costs[s]
+        avg_ms = ms / n
+        if bound == "hbm":
+            ach = amt / (avg_ms * 1e-3) / 1e9
+            per_stage[s] = dict(avg_ms=round(avg_ms, 5), bound="hbm", achieved_GBs=round(ach, 1),
+                                frac=round(ach / PEAK_HBM_GBS, 4), bytes=int(amt))
+        else:
+            ach = amt / (avg_ms * 1e-3) / 1e12
+            per_stage[s] = dict(avg_ms=round(avg_ms, 5), bound="alu", achieved_TFLOPs=round(ach, 3),
+                                frac=round(ach / PEAK_FP64_TFLOPS, 4), flops=int(amt))
+    dom = max(per_stage, key=lambda s: per_stage[s]["avg_ms"])
+    d = per_stage[dom]
+    if d["bound"] == "hbm":
+        roof = {"bound": "hbm", "kernel": pa.Wfp2d.KERNELS[pa.Wfp2d.STAGES.index(dom)], "achieved": d["achieved_GBs"],
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": d["frac"], "traffic": None}
+    else:
+        roof = {"bound": "alu", "kernel": pa.Wfp2d.KERNELS[pa.Wfp2d.STAGES.index(dom)], "achieved": d["achieved_TFLOPs"],
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": d["frac"], "traffic": None}
+    hbm_bytes = sum(costs[s][1] for s in per_stage if costs[s][0] == "hbm")
+    step_hbm_frac = hbm_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS
+
+    # ---- CPU oracle on a bounded sample (+ a full-scale parity check of that sample) ----
+    cpu = None
+    sample_err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(77)
+        ti = rng.choice(w.Nx, size=args.cpu_sample_targets, replace=False)
+        t_rep = step_reported * w.dt
+        u_gpu = u.cpu().numpy()[ti]
+        nth = oracle.threads()
+        c0 = time.perf_counter()
+        u_ref = oracle.u_workload(w, ti, [t_rep], self_mode=1, delta=info["delta"], b=info["b"])[:, 0]
+        t_cpu = time.perf_counter() - c0
+        # the full job (all Nx targets x K steps) would take t_cpu * Nx * K / n_samples
+        rate = w.M * len(ti) / (t_cpu * w.Nx)
+        cpu = {"value": rate, "unit": "source*steps/s", "cores": nth, "kind": "oracle",
+               "sample": f"{len(ti)} seeded target(s) x 1 step (t_{step_reported}) x all {w.M} sources, "
+                         f"{t_cpu:.1f} s; rate = M * samples / (t_sample * Nx)"}
+        sample_err = float(np.linalg.norm(u_gpu - u_ref) / max(np.linalg.norm(u_ref), 1e-300))
+        log(f"[bench] oracle sample {t_cpu:.1f}s on {nth} threads; GPU vs oracle rel err {sample_err:.2e}")
+
+    out = {
+        "metric": "source*timesteps/sec at 1e-6 rel L2 error; % of HBM roofline",
+        "value": value,
+        "unit": "source*steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic (seeded closed-form signatures, random sources)",
+        "config": {"workload": w.name, "M": w.M, "Nx": w.Nx, "dt": w.dt, "W": w.W, "p": w.p, "eps": w.tol,
+                   "timed_steps": f"{args.warmup + 1}..{args.warmup + K} (reported u at t_{step_reported - K + 1}.."
+                                  f"t_{step_reported})", "precision": args.precision,
+                   "n_modes": info["n_modes"], "nf": info["nf"], "local_pairs": info["n_local_pairs"]},
+        "roofline": roof,
+        "hbm_roofline_step_frac": round(step_hbm_frac, 4),
+        "stages": per_stage,
+        "cpu_baseline": cpu,
+        "sample_rel_err_vs_oracle": sample_err,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

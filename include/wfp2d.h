@@ -164,6 +164,19 @@ const char *wfp2d_last_error(wfp2d_plan plan);
 wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t *bytes);
 
 /*
+ * Per-stage timing with HIP events recorded on the plan's stream around every
+ * launch of the hot path (for measurement; adds one event pair per launch).
+ * wfp2d_set_timing(plan, 1) clears and enables the accumulators, 0 disables.
+ * wfp2d_get_timing synchronises the stream and writes, for stage s < n:
+ * ms[s] = total milliseconds, launches[s] = number of launches since enabling.
+ * Stages: 0 ingest, 1 spread, 2 type-1 row FFT, 3 type-1 column FFT,
+ * 4 Hermitian split, 5 near update, 6 far update, 7 type-2 column FFT,
+ * 8 type-2 row FFT, 9 interpolation, 10 local part, 11 combine (n <= 12).
+ * Errors: ERR_ARG, ERR_DEVICE. */
+wfp2d_status wfp2d_set_timing(wfp2d_plan plan, int32_t enable);
+wfp2d_status wfp2d_get_timing(wfp2d_plan plan, double *ms, int64_t *launches, int32_t n);
+
+/*
  * Host-only evaluation of the plan's precomputation, without a device (for
  * tests of the set-up numerics).  All pointers are host pointers; nothing is
  * allocated on a device.  what:
@@ -179,6 +192,8 @@ wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t 
  *     evaluate them): same in/out as 4.
  *   6 blending function (eq. KBblending): in = {width, b, t_1..t_k};
  *     out = [k][2] = (phi, phi').
+ *   7 layout of the local-weight tables: in as 4; out = {sub-panels, regular
+ *     sub-panels, levels, max relative fit error, log2 splits of panel 0..W-1}.
  * Returns ERR_ARG for an unknown what, short buffers or bad parameters; on
  * success out_count (if not NULL) receives the number of doubles written. */
 wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, double *out, int64_t n_out,

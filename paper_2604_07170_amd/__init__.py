@@ -76,8 +76,10 @@ def load_library():
     lib.wfp2d_last_error.restype = ctypes.c_char_p
     lib.wfp2d_debug_copy.argtypes = [vp, i32, vp, ctypes.POINTER(i64)]
     lib.wfp2d_host_eval.argtypes = [i32, dp, i64, dp, i64, ctypes.POINTER(i64)]
+    lib.wfp2d_set_timing.argtypes = [vp, i32]
+    lib.wfp2d_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), i32]
     for f in ("wfp2d_default_opts", "wfp2d_init", "wfp2d_step", "wfp2d_evaluate", "wfp2d_query", "wfp2d_destroy",
-              "wfp2d_debug_copy", "wfp2d_host_eval"):
+              "wfp2d_debug_copy", "wfp2d_host_eval", "wfp2d_set_timing", "wfp2d_get_timing"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -179,6 +181,22 @@ class Wfp2d:
             raise ValueError("out must be a contiguous float64 CUDA tensor with Nx elements")
         self._check(self.lib.wfp2d_evaluate(self.h, ctypes.c_void_p(out.data_ptr())))
         return out
+
+    STAGES = ("ingest", "spread", "fft_rows1", "fft_cols1", "split", "near", "far", "fft_cols2", "fft_rows2",
+              "interp", "local", "combine")
+    KERNELS = ("k_ingest", "k_spread", "k_rows1", "k_cols1", "k_split", "k_near", "k_far", "k_cols2", "k_rows2",
+               "k_interp", "k_local", "k_combine")
+
+    def set_timing(self, enable: bool):
+        self._check(self.lib.wfp2d_set_timing(self.h, 1 if enable else 0))
+
+    def get_timing(self) -> dict:
+        """{stage: (total ms, launches)} since timing was enabled (synchronises the stream)."""
+        n = len(self.STAGES)
+        ms = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int64)
+        self._check(self.lib.wfp2d_get_timing(self.h, _dp(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n))
+        return {s: (float(ms[i]), int(cnt[i])) for i, s in enumerate(self.STAGES)}
 
     def debug(self, what: int) -> np.ndarray:
         inf = self.info()

@@ -50,7 +50,48 @@ Plan::~Plan()
 {
     if (stream) (void)hipStreamSynchronize(stream);
     else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void *ptr : allocs) (void)hipFree(ptr);
+}
+
+// fold the elapsed times of the recorded event pairs into the accumulators
+static void drain_timing(Plan &p)
+{
+    if (p.ev_stage.empty()) return;
+    hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+    for (size_t i = 0; i < p.ev_stage.size(); ++i) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, p.ev_pool[2 * i], p.ev_pool[2 * i + 1]), "hipEventElapsedTime");
+        p.stage_ms[p.ev_stage[i]] += ms;
+        p.stage_n[p.ev_stage[i]] += 1;
+    }
+    p.ev_stage.clear();
+}
+
+// run one launcher, bracketed by events when timing is enabled
+template <class F>
+static void timed(Plan &p, int stage, const char *what, F &&launch)
+{
+    if (!p.timing) {
+        hip_check(launch(), what);
+        return;
+    }
+    size_t k = p.ev_stage.size();
+    if (2 * k + 2 > p.ev_pool.size()) {
+        if (k >= 256) {
+            drain_timing(p);
+            k = 0;
+        }
+        while (2 * k + 2 > p.ev_pool.size()) {
+            hipEvent_t e;
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+            p.ev_pool.push_back(e);
+        }
+    }
+    hip_check(hipEventRecord(p.ev_pool[2 * k], p.stream), "hipEventRecord");
+    hip_check(launch(), what);
+    hip_check(hipEventRecord(p.ev_pool[2 * k + 1], p.stream), "hipEventRecord");
+    p.ev_stage.push_back(stage);
 }
 
 template <class T>
@@ -186,7 +227,8 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         far_cls[f] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), far_key[f]) - keys.begin());
 
     // ---------------- geometry: sort by local cell ----------------
-    p.ncell = std::max(1, (int)std::floor(2.0 / p.delta));
+    // cells of side >= delta/2: every target within delta of a source lies in the 5 x 5 block of cells around it
+    p.ncell = std::max(1, (int)std::floor(4.0 / p.delta));
     p.cell_h = 2.0 / p.ncell;
     auto cell_of = [&](double x, double y) {
         int cx = std::min(p.ncell - 1, std::max(0, (int)std::floor((x + 1.0) / p.cell_h)));
@@ -205,6 +247,9 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     std::iota(tperm.begin(), tperm.end(), 0);
     std::stable_sort(tperm.begin(), tperm.end(), [&](int32_t a, int32_t b) { return tcell[a] < tcell[b]; });
     for (int64_t i = 0; i < Nx; ++i) trank[tperm[i]] = (int32_t)i;
+    std::vector<int32_t> tcell_start((size_t)p.ncell * p.ncell + 1, 0);
+    for (int64_t i = 0; i < Nx; ++i) tcell_start[tcell[i] + 1]++;
+    for (size_t c = 1; c < tcell_start.size(); ++c) tcell_start[c] += tcell_start[c - 1];
     std::vector<double2> sxy(M), txy(Nx);
     std::vector<int32_t> tcell_sorted(Nx);
     for (int64_t j = 0; j < M; ++j) sxy[j] = make_double2(src_xy[2 * sperm[j]], src_xy[2 * sperm[j] + 1]);
@@ -322,8 +367,8 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         const double d2 = p.delta * p.delta;
         for (int64_t i = 0; i < Nx; ++i) {
             int c = tcell_sorted[i], cx = c % p.ncell, cy = c / p.ncell;
-            for (int yy = std::max(0, cy - 1); yy <= std::min(p.ncell - 1, cy + 1); ++yy)
-                for (int xx = std::max(0, cx - 1); xx <= std::min(p.ncell - 1, cx + 1); ++xx) {
+            for (int yy = std::max(0, cy - 2); yy <= std::min(p.ncell - 1, cy + 2); ++yy)
+                for (int xx = std::max(0, cx - 2); xx <= std::min(p.ncell - 1, cx + 2); ++xx) {
                     int cc = yy * p.ncell + xx;
                     for (int32_t j = cell_start[cc]; j < cell_start[cc + 1]; ++j) {
                         double dx = txy[i].x - sxy[j].x, dy = txy[i].y - sxy[j].y, r2 = dx * dx + dy * dy;
@@ -402,12 +447,30 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     p.d_ul = p.alloc<double>(Nx);
     p.d_cell_start = p.alloc<int32_t>((int64_t)cell_start.size());
     upload(p.d_cell_start, cell_start);
-    p.d_tgt_cell = p.alloc<int32_t>(Nx);
-    upload(p.d_tgt_cell, tcell_sorted);
+    p.d_tcell_start = p.alloc<int32_t>((int64_t)tcell_start.size());
+    upload(p.d_tcell_start, tcell_start);
     p.d_subs = p.alloc<SubPanel>(p.n_sub);
     upload(p.d_subs, LT.subs);
-    p.d_cheb = p.alloc<double>((int64_t)LT.coef.size());
-    upload(p.d_cheb, LT.coef);
+    {
+        // tables scaled by 1/(2 pi) (eq. local2); regular sub-panels also in [sub][c][d] order
+        const double s2pi = 0.5 / M_PI;
+        std::vector<double> cheb(LT.coef);
+        for (double &v : cheb) v *= s2pi;
+        p.d_cheb = p.alloc<double>((int64_t)cheb.size());
+        upload(p.d_cheb, cheb);
+        p.n_reg = LT.dy_base;
+        const int nl = LT.nlev, D = kChebDeg;
+        std::vector<double> creg((size_t)p.n_reg * D * nl);
+        for (int sp = 0; sp < p.n_reg; ++sp)
+            for (int d = 0; d < nl; ++d)
+                for (int c = 0; c < D; ++c)
+                    creg[((size_t)sp * D + c) * nl + d] = s2pi * LT.coef[((size_t)sp * nl + d) * D + c];
+        p.d_creg = p.alloc<double>((int64_t)creg.size());
+        upload(p.d_creg, creg);
+        if (nl > kLocalMaxLevels) fail(WFP2D_ERR_INFEASIBLE, "too many sigma levels for the local kernel (W + p too large)");
+        p.local_sc = std::min<int>(kLocalMaxSrc, std::min(kLocalPsi / (p.n_reg * D), kLocalSig / nl));
+        if (p.local_sc < 1) fail(WFP2D_ERR_INFEASIBLE, "local-weight tables too large for the local kernel");
+    }
     p.d_panel_base = p.alloc<int32_t>(p.W);
     upload(p.d_panel_base, LT.panel_base);
     p.d_panel_l2n = p.alloc<int32_t>(p.W);
@@ -420,16 +483,17 @@ static void do_step(Plan &p, const double *sigma)
     hip_check(hipSetDevice(p.device), "hipSetDevice");
     const Geom &g = p.g;
     p.steps += 1;
-    hip_check(launch_ingest(p, sigma, p.steps % g.sig_depth), "ingest");
+    const int64_t slot = p.steps % g.sig_depth;
+    timed(p, 0, "ingest", [&] { return launch_ingest(p, sigma, slot); });
     const int64_t m = p.steps - p.lookahead;
     if (m < 1) return;
     auto md = [](int64_t a, int64_t b) { return ((a % b) + b) % b; };
-    hip_check(launch_spread(p, md(m, g.sig_depth), md(m - p.LA, g.sig_depth)), "spread");
-    hip_check(launch_fft_rows1(p), "fft rows (type 1)");
-    hip_check(launch_fft_cols1(p), "fft columns (type 1)");
-    hip_check(launch_split(p, md(m, p.W), md(m - p.LA, p.W)), "hermitian split");
-    hip_check(launch_near(p, m), "near-history update");
-    hip_check(launch_far(p, m), "far-history update");
+    timed(p, 1, "spread", [&] { return launch_spread(p, md(m, g.sig_depth), md(m - p.LA, g.sig_depth)); });
+    timed(p, 2, "fft rows (type 1)", [&] { return launch_fft_rows1(p); });
+    timed(p, 3, "fft columns (type 1)", [&] { return launch_fft_cols1(p); });
+    timed(p, 4, "hermitian split", [&] { return launch_split(p, md(m, p.W), md(m - p.LA, p.W)); });
+    timed(p, 5, "near-history update", [&] { return launch_near(p, m); });
+    timed(p, 6, "far-history update", [&] { return launch_far(p, m); });
 }
 
 static void do_evaluate(Plan &p, double *u)
@@ -437,14 +501,17 @@ static void do_evaluate(Plan &p, double *u)
     hip_check(hipSetDevice(p.device), "hipSetDevice");
     const int64_t m = p.steps - p.lookahead;
     if (m < 1) {
-        hip_check(launch_combine(p, u, 1), "combine");
+        timed(p, 11, "combine", [&] { return launch_combine(p, u, 1); });
         return;
     }
-    hip_check(launch_fft_cols2(p), "fft columns (type 2)");
-    hip_check(launch_fft_rows2(p), "fft rows (type 2)");
-    hip_check(launch_interp(p), "interpolation");
-    hip_check(launch_local(p, m), "local part");
-    hip_check(launch_combine(p, u, 0), "combine");
+    timed(p, 7, "fft columns (type 2)", [&] { return launch_fft_cols2(p); });
+    timed(p, 8, "fft rows (type 2)", [&] { return launch_fft_rows2(p); });
+    timed(p, 9, "interpolation", [&] { return launch_interp(p); });
+    timed(p, 10, "local part", [&] {
+        hipError_t e = launch_zero_f64(p, p.d_ul, p.Nx);
+        return e != hipSuccess ? e : launch_local(p, m);
+    });
+    timed(p, 11, "combine", [&] { return launch_combine(p, u, 0); });
 }
 
 }  // namespace wfp2d
@@ -679,6 +746,35 @@ wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t 
     return WFP2D_OK;
 }
 
+wfp2d_status wfp2d_set_timing(wfp2d_plan plan, int32_t enable)
+{
+    if (!plan) return WFP2D_ERR_ARG;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        drain_timing(p);
+        for (int s = 0; s < Plan::kStages; ++s) {
+            p.stage_ms[s] = 0.0;
+            p.stage_n[s] = 0;
+        }
+        p.timing = enable != 0;
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_get_timing(wfp2d_plan plan, double *ms, int64_t *launches, int32_t n)
+{
+    if (!plan || !ms || n < 0) return WFP2D_ERR_ARG;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        drain_timing(p);
+        for (int s = 0; s < n && s < Plan::kStages; ++s) {
+            ms[s] = p.stage_ms[s];
+            if (launches) launches[s] = p.stage_n[s];
+        }
+    });
+    return WFP2D_OK;
+}
+
 wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, double *out, int64_t n_out,
                              int64_t *out_count)
 {
@@ -734,6 +830,23 @@ wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, doubl
                 LocalTable T = build_local_table(LW, 40, 1e-12);
                 for (int64_t i = 0; i < k; ++i) local_table_eval(T, dt, W, in[5 + i], out + i * LW.nlev);
             }
+            break;
+        }
+        case 7: {
+            if (n_in < 5) fail(WFP2D_ERR_ARG, "need dt, W, p, lookahead, tol");
+            const double dt = in[0], tol = in[4];
+            const int W = (int)in[1], p = (int)in[2];
+            int look = (int)in[3];
+            if (look < 0) look = (p + 1) / 2 - 1;
+            Blend phi(W * dt, std::log(1.0 / tol), 160);
+            LocalWeights LW(dt, W, p, -look, phi);
+            LocalTable T = build_local_table(LW, 40, 1e-12);
+            need(4 + W);
+            out[0] = (double)T.subs.size();
+            out[1] = (double)T.dy_base;
+            out[2] = (double)T.nlev;
+            out[3] = T.max_err;
+            for (int k = 0; k < W; ++k) out[4 + k] = (double)T.panel_l2n[k];
             break;
         }
         case 6: {

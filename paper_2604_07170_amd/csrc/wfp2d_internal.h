@@ -15,7 +15,14 @@ namespace wfp2d {
 constexpr int kTile = 32;          // spreading / interpolation tile edge (fine-grid points)
 constexpr int kChunk = 256;        // modes per work chunk of the per-mode kernels
 constexpr int kNsoe = 640;         // SOE terms: 20 dyadic panels x 32 Gauss-Legendre nodes (Sec. 2.3)
-constexpr int kChebDeg = 16;       // Chebyshev terms per local-weight sub-panel
+constexpr int kChebDeg = 24;       // Chebyshev terms per local-weight sub-panel
+constexpr int kLocalThreads = 512; // local kernel: threads per workgroup (one target each)
+constexpr int kLocalPsi = 4096;    //   LDS doubles for the per-source Chebyshev profiles
+constexpr int kLocalSig = 640;     //   LDS doubles for the sources' sigma levels
+constexpr int kLocalMaxSrc = 16;   //   sources per chunk (upper bound)
+constexpr int kLocalMaxLevels = 64;
+constexpr int kLocalQueue = 256;   //   queued pairs with r < dt/2 per chunk
+constexpr int kLocalOwn = 2;       //   targets owned per thread (regions up to 1024 targets in one pass)
 
 // Work chunk of a per-mode kernel: modes [off, off+cnt) of packed column nx,
 // whose first mode has ny = ny0 (ny increases by one per mode).
@@ -27,7 +34,8 @@ struct ModeChunk {
 struct SubPanel {
     double ra, rb;   // r range
     double c;        // > 0: Chebyshev variable in u = sqrt(c - r); 0: linear in r
-    double ua, ub;   // sqrt(c - ra), sqrt(c - rb) when c > 0
+    double ua, ub;   // variable at ra and rb: sqrt(c - r) when c > 0, else r
+    double inv;      // 1 / (ua - ub): Chebyshev coordinate x = (2 v - ua - ub) * inv
 };
 
 // Parameters every kernel needs (passed by value).
@@ -55,6 +63,7 @@ hipError_t launch_fft_cols2(Plan &p);
 hipError_t launch_fft_rows2(Plan &p);
 hipError_t launch_interp(Plan &p);
 hipError_t launch_local(Plan &p, int64_t m);
+hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n);
 hipError_t launch_combine(Plan &p, double *u_out, int zero);
 hipError_t launch_zero(Plan &p, void *ptr, int64_t bytes);
 
@@ -129,14 +138,24 @@ struct Plan {
     int32_t ncell = 1;
     double cell_h = 2.0;
     int32_t *d_cell_start = nullptr;  // sources per cell (sorted), size ncell^2 + 1
-    int32_t *d_tgt_cell = nullptr;    // cell of each sorted target
+    int32_t *d_tcell_start = nullptr; // targets per cell (sorted), size ncell^2 + 1
     SubPanel *d_subs = nullptr;
-    double *d_cheb = nullptr;         // [n_sub][nlev][kChebDeg]
+    double *d_cheb = nullptr;         // [n_sub][nlev][kChebDeg], scaled by 1/(2 pi)
+    double *d_creg = nullptr;         // regular sub-panels [n_reg][kChebDeg][nlev], scaled by 1/(2 pi)
+    int32_t n_reg = 0, local_sc = 1;  // regular sub-panels; sources per chunk in the local kernel
     int32_t *d_panel_base = nullptr;  // regular panel k -> first sub-panel, and log2 count
     int32_t *d_panel_l2n = nullptr;
     int32_t dy_base = 0, n_dy = 0;
 
     std::string err;
+
+    // stage timing (events recorded around launches when enabled)
+    static constexpr int kStages = 12;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;             // pairs: start, stop
+    std::vector<int> ev_stage;                   // stage of each recorded pair
+    double stage_ms[kStages] = {};
+    int64_t stage_n[kStages] = {};
 
     template <class T>
     T *alloc(int64_t count);

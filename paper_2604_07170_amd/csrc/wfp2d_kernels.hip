@@ -514,81 +514,250 @@ __global__ __launch_bounds__(256) void k_interp(const R *__restrict__ cgrid, con
 }
 
 // ---------------------------------------------------------------------------
-// Local part (Sec. 6, eq. ul_GL with eq. sigInterp): for each target, the
-// sources within delta in the 3x3 neighbouring cells; eta_d(r) from the
-// Chebyshev sub-panel tables; u_l = (1/2pi) sum_j sum_d eta_d(r) sigma_j(t_{m-d}).
+// Local part (Sec. 6, eq. ul_GL with eq. sigInterp):
+//   u_l(x_i, t_m) = (1/2pi) sum_{j: 0 < r_ij < delta} f_j(r_ij),
+//   f_j(r) = sum_d eta_d(r) sigma_j(t_{m-d}),
+// where eta_d is held as Chebyshev series on sub-panels of r.  For every
+// regular sub-panel P (r >= dt/2) the kernel first synthesises, per source,
+// the Chebyshev coefficients of f_j on P:  psi_{j,P,c} = sum_d C_{P,c,d} sigma_{j,d}
+// (a small dense contraction), then each source-target pair costs one Clenshaw
+// evaluation.  One workgroup owns one source cell (side >= delta/2); its
+// targets are the 5 x 5 block of target cells around it.  Pairs with
+// r < dt/2 (dyadic sub-panels, about 1e-3 of all pairs) are queued and
+// evaluated level by level, one wavefront per pair.  Per-target sums are
+// accumulated in LDS and added to u_l with one FP64 atomic per (target, cell).
 // ---------------------------------------------------------------------------
 struct LocalArgs {
     const double2 *txy, *sxy;
-    const int32_t *tcell, *cell_start;
+    const int32_t *scell_start, *tcell_start;
     const SubPanel *subs;
-    const double *cheb;
+    const double *cheb, *creg;
     const int32_t *pbase, *pl2n;
     const double *sig;
     double *ul;
-    int ncell, dy_base, n_dy;
-    double delta;
+    int ncell, n_reg, dy_base, n_dy, sc;
+    double delta, inv_dt;
 };
 
-__device__ __forceinline__ double cheb_eval(const double *__restrict__ c, double x)
+__device__ __forceinline__ double cheb_eval(const double *c, double x)
 {
     double b1 = 0.0, b2 = 0.0;
+    const double tx = 2.0 * x;
 #pragma unroll
     for (int k = kChebDeg - 1; k >= 1; --k) {
-        const double b0 = fma(2.0 * x, b1, c[k] - b2);
+        const double b0 = fma(tx, b1, c[k] - b2);
         b2 = b1;
         b1 = b0;
     }
     return fma(x, b1, c[0] - b2);
 }
 
-__global__ __launch_bounds__(256) void k_local(LocalArgs A, int64_t m, Geom g)
+// two independent Clenshaw recurrences interleaved (instruction-level parallelism)
+__device__ __forceinline__ void cheb_eval2(const double *c0, double x0, const double *c1, double x1, double &v0, double &v1)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.Nx) return;
-    const double2 x = A.txy[i];
-    const int c = A.tcell[i], cx = c % A.ncell, cy = c / A.ncell;
+    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+    const double t0 = 2.0 * x0, t1 = 2.0 * x1;
+#pragma unroll
+    for (int k = kChebDeg - 1; k >= 1; --k) {
+        const double a0 = fma(t0, a1, c0[k] - a2);
+        const double b0 = fma(t1, b1, c1[k] - b2);
+        a2 = a1;
+        a1 = a0;
+        b2 = b1;
+        b1 = b0;
+    }
+    v0 = fma(x0, a1, c0[0] - a2);
+    v1 = fma(x1, b1, c1[0] - b2);
+}
+
+__device__ __forceinline__ double sub_coord(const SubPanel &sp, double r)
+{
+    const double v = sp.c > 0.0 ? sqrt(fmax(0.0, sp.c - r)) : r;
+    return fmin(1.0, fmax(-1.0, (2.0 * v - sp.ua - sp.ub) * sp.inv));
+}
+
+__device__ __forceinline__ int regular_sub(const LocalArgs &A, double rr, int W)
+{
+    const int k = min((int)rr, W - 1);
+    const double lo = k == 0 ? 0.5 : (double)k, sc = k == 0 ? 2.0 : 1.0;
+    const int nsp = 1 << A.pl2n[k];
+    return A.pbase[k] + min((int)((rr - lo) * sc * nsp), nsp - 1);
+}
+
+__device__ __forceinline__ int dyadic_sub(const LocalArgs &A, double rr)
+{
+    int e;
+    frexp(rr, &e);
+    return A.dy_base + min(-e, A.n_dy) - 1;
+}
+
+// eta-weighted sum over levels for a pair with r < dt/2 (dyadic sub-panel)
+__device__ double dyadic_direct(const LocalArgs &A, const double *sg, int nlev, double r, double rr)
+{
+    const int sub = dyadic_sub(A, rr);
+    const double xc = sub_coord(A.subs[sub], r);
+    double v = 0.0;
+    for (int d = 0; d < nlev; ++d) v = fma(cheb_eval(A.cheb + ((size_t)sub * nlev + d) * kChebDeg, xc), sg[d], v);
+    return v;
+}
+
+__device__ __forceinline__ int64_t sig_slot(int64_t m, int d, const Geom &g)
+{
+    const int64_t lvl = m - (g.lev_min + d);
+    return ((lvl % g.sig_depth) + g.sig_depth) % g.sig_depth;
+}
+
+__global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, int64_t m, Geom g)
+{
+    __shared__ double psi[kLocalPsi];          // [sc][n_reg][D]
+    __shared__ double sigs[kLocalSig];         // [sc][nlev]
+    __shared__ double2 spos[kLocalMaxSrc];
+    __shared__ int qs[kLocalQueue], qt[kLocalQueue];
+    __shared__ double qr[kLocalQueue];
+    __shared__ int qn;
+    __shared__ int rbeg[5], rcum[6];
+
+    const int cell = blockIdx.x, n = A.ncell;
+    const int cx = cell % n, cy = cell / n;
+    const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
+    if (s0 == s1) return;                       // uniform: no sources in this cell
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int nlev = g.nlev, nreg = A.n_reg, D = kChebDeg;
     const double d2 = A.delta * A.delta;
-    double acc = 0.0;
-    for (int yy = max(0, cy - 1); yy <= min(A.ncell - 1, cy + 1); ++yy)
-        for (int xx = max(0, cx - 1); xx <= min(A.ncell - 1, cx + 1); ++xx) {
-            const int cc = yy * A.ncell + xx;
-            for (int j = A.cell_start[cc]; j < A.cell_start[cc + 1]; ++j) {
-                const double2 y = A.sxy[j];
-                const double dx = x.x - y.x, dy = x.y - y.y, r2 = dx * dx + dy * dy;
-                if (!(r2 > 0.0 && r2 < d2)) continue;
-                const double r = sqrt(r2);
-                const double rr = r / g.dt;
-                int sub;
-                if (rr >= 0.5) {
-                    const int k = min((int)rr, g.W - 1);
-                    const double lo = k == 0 ? 0.5 : (double)k, wd = k == 0 ? 0.5 : 1.0;
-                    const int ns = 1 << A.pl2n[k];
-                    sub = A.pbase[k] + min((int)((rr - lo) / wd * ns), ns - 1);
-                } else {
-                    int e;
-                    frexp(rr, &e);
-                    int idx = min(-e, A.n_dy);
-                    sub = A.dy_base + idx - 1;
-                }
-                const SubPanel sp = A.subs[sub];
-                double xc;
-                if (sp.c > 0.0) {
-                    const double u = sqrt(fmax(0.0, sp.c - r));
-                    xc = (2.0 * u - sp.ua - sp.ub) / (sp.ua - sp.ub);
-                } else {
-                    xc = (2.0 * r - sp.ra - sp.rb) / (sp.rb - sp.ra);
-                }
-                xc = fmin(1.0, fmax(-1.0, xc));
-                const double *cf = A.cheb + (size_t)sub * g.nlev * kChebDeg;
-                for (int d = 0; d < g.nlev; ++d) {
-                    const int64_t lvl = m - (g.lev_min + d);
-                    const int64_t slot = ((lvl % g.sig_depth) + g.sig_depth) % g.sig_depth;
-                    acc = fma(cheb_eval(cf + d * kChebDeg, xc), A.sig[slot * g.M + j], acc);
-                }
+
+    // the 5 x 5 block of target cells: up to 5 contiguous runs of sorted targets
+    if (tid == 0) {
+        int cum = 0, r = 0;
+        const int xa = max(0, cx - 2), xb = min(n - 1, cx + 2);
+        for (int yy = max(0, cy - 2); yy <= min(n - 1, cy + 2); ++yy, ++r) {
+            const int b = A.tcell_start[yy * n + xa], e = A.tcell_start[yy * n + xb + 1];
+            rbeg[r] = b;
+            rcum[r] = cum;
+            cum += e - b;
+        }
+        for (; r < 5; ++r) {
+            rbeg[r] = 0;
+            rcum[r] = cum;
+        }
+        rcum[5] = cum;
+    }
+    __syncthreads();
+    const int NT = rcum[5];
+
+    const int bd = blockDim.x;
+    for (int tc0 = 0; tc0 < NT; tc0 += kLocalOwn * bd) {
+        // each thread owns up to kLocalOwn targets of the block and accumulates in registers
+        const int nown = min(kLocalOwn, (NT - tc0 + bd - 1) / bd);
+        int tg[kLocalOwn];
+        double2 x[kLocalOwn];
+        double acc[kLocalOwn];
+#pragma unroll
+        for (int j = 0; j < kLocalOwn; ++j) {
+            const int kk = tc0 + tid + j * bd;
+            tg[j] = -1;
+            x[j] = make_double2(1e30, 1e30);
+            acc[j] = 0.0;
+            if (j < nown && kk < NT) {
+                int r = 0;
+                while (r < 4 && kk >= rcum[r + 1]) ++r;
+                tg[j] = rbeg[r] + (kk - rcum[r]);
+                x[j] = A.txy[tg[j]];
             }
         }
-    A.ul[i] = acc * (0.5 / M_PI);
+        for (int sb = s0; sb < s1; sb += A.sc) {
+            const int ns = min(A.sc, s1 - sb);
+            for (int e = tid; e < ns * nlev; e += bd) {
+                const int sidx = e / nlev, d = e - sidx * nlev;
+                sigs[sidx * nlev + d] = A.sig[sig_slot(m, d, g) * g.M + sb + sidx];
+            }
+            if (tid < ns) spos[tid] = A.sxy[sb + tid];
+            if (tid == 0) qn = 0;
+            __syncthreads();
+            // profile coefficients psi = C sigma on every regular sub-panel
+            for (int e = tid; e < nreg * D; e += bd) {
+                const double *cf = A.creg + (size_t)e * nlev;
+                double pa[kLocalMaxSrc];
+#pragma unroll
+                for (int q = 0; q < kLocalMaxSrc; ++q) pa[q] = 0.0;
+                for (int d = 0; d < nlev; ++d) {
+                    const double c = cf[d];
+#pragma unroll
+                    for (int q = 0; q < kLocalMaxSrc; ++q)
+                        if (q < ns) pa[q] = fma(c, sigs[q * nlev + d], pa[q]);
+                }
+                const int P = e / D, c = e - P * D;
+#pragma unroll
+                for (int q = 0; q < kLocalMaxSrc; ++q)
+                    if (q < ns) psi[(q * nreg + P) * D + c] = pa[q];
+            }
+            __syncthreads();
+            // pairs (owned targets) x (chunk sources), two sources at a time
+#pragma unroll
+            for (int j = 0; j < kLocalOwn; ++j) {
+                if (j >= nown) continue;
+                const double2 xj = x[j];
+                for (int sidx = 0; sidx < ns; sidx += 2) {
+                    const bool two = sidx + 1 < ns;
+                    const int s2 = two ? sidx + 1 : sidx;
+                    const double2 y0 = spos[sidx], y1 = spos[s2];
+                    const double ax = xj.x - y0.x, ay = xj.y - y0.y, bx = xj.x - y1.x, by = xj.y - y1.y;
+                    const double ra2 = ax * ax + ay * ay, rb2 = bx * bx + by * by;
+                    bool ha = ra2 > 0.0 && ra2 < d2, hb = two && rb2 > 0.0 && rb2 < d2;
+                    if (!(ha || hb)) continue;
+                    const double ra = sqrt(ra2), rb = sqrt(rb2);
+                    const double rra = ra * A.inv_dt, rrb = rb * A.inv_dt;
+                    if ((ha && rra < 0.5) || (hb && rrb < 0.5)) {   // rare: queue, evaluated level by level
+                        const bool qa = ha && rra < 0.5, qb = hb && rrb < 0.5;
+                        const int q = atomicAdd(&qn, (qa ? 1 : 0) + (qb ? 1 : 0));
+                        int qq = q;
+                        if (qa) {
+                            if (qq < kLocalQueue) { qs[qq] = sidx; qt[qq] = tg[j]; qr[qq] = ra; }
+                            else acc[j] += dyadic_direct(A, sigs + sidx * nlev, nlev, ra, rra);
+                            ++qq;
+                            ha = false;
+                        }
+                        if (qb) {
+                            if (qq < kLocalQueue) { qs[qq] = s2; qt[qq] = tg[j]; qr[qq] = rb; }
+                            else acc[j] += dyadic_direct(A, sigs + s2 * nlev, nlev, rb, rrb);
+                            hb = false;
+                        }
+                        if (!(ha || hb)) continue;
+                    }
+                    const int sa = ha ? regular_sub(A, rra, g.W) : 0;
+                    const int sbb = hb ? regular_sub(A, rrb, g.W) : 0;
+                    const double xa = ha ? sub_coord(A.subs[sa], ra) : 0.0;
+                    const double xb = hb ? sub_coord(A.subs[sbb], rb) : 0.0;
+                    double va, vb;
+                    cheb_eval2(psi + (sidx * nreg + sa) * D, xa, psi + (s2 * nreg + sbb) * D, xb, va, vb);
+                    acc[j] += (ha ? va : 0.0) + (hb ? vb : 0.0);
+                }
+            }
+            __syncthreads();
+            // queued pairs with r < dt/2: one wavefront per pair, lanes over levels
+            const int nq = min(qn, kLocalQueue);
+            for (int q = wave; q < nq; q += nwave) {
+                const int sidx = qs[q];
+                const double r = qr[q];
+                const int sub = dyadic_sub(A, r * A.inv_dt);
+                const double xc = sub_coord(A.subs[sub], r);
+                double v = 0.0;
+                for (int d = lane; d < nlev; d += 64)
+                    v = fma(cheb_eval(A.cheb + ((size_t)sub * nlev + d) * D, xc), sigs[sidx * nlev + d], v);
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                if (lane == 0) unsafeAtomicAdd(&A.ul[qt[q]], v);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < kLocalOwn; ++j)
+            if (tg[j] >= 0 && acc[j] != 0.0) unsafeAtomicAdd(&A.ul[tg[j]], acc[j]);
+    }
+}
+
+__global__ void k_zero_f64(double *__restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
 }
 
 // u (caller order) = u_h + u_l, or zeros before the first reported step
@@ -735,19 +904,29 @@ hipError_t launch_local(Plan &p, int64_t m)
     LocalArgs A;
     A.txy = p.d_tgt_xy;
     A.sxy = p.d_src_xy;
-    A.tcell = p.d_tgt_cell;
-    A.cell_start = p.d_cell_start;
+    A.scell_start = p.d_cell_start;
+    A.tcell_start = p.d_tcell_start;
     A.subs = p.d_subs;
     A.cheb = p.d_cheb;
+    A.creg = p.d_creg;
     A.pbase = p.d_panel_base;
     A.pl2n = p.d_panel_l2n;
     A.sig = p.d_sig;
     A.ul = p.d_ul;
     A.ncell = p.ncell;
+    A.n_reg = p.n_reg;
     A.dy_base = p.dy_base;
     A.n_dy = p.n_dy;
+    A.sc = p.local_sc;
     A.delta = p.delta;
-    hipLaunchKernelGGL(k_local, dim3(nblk(p.Nx, 256)), dim3(256), 0, p.stream, A, m, p.g);
+    A.inv_dt = 1.0 / p.dt;
+    hipLaunchKernelGGL(k_local, dim3((unsigned)(p.ncell * p.ncell)), dim3(kLocalThreads), 0, p.stream, A, m, p.g);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n)
+{
+    hipLaunchKernelGGL(k_zero_f64, dim3(nblk(n, 256)), dim3(256), 0, p.stream, ptr, n);
     return hipGetLastError();
 }
 

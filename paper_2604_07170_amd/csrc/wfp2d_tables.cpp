@@ -293,11 +293,8 @@ void LocalWeights::eta(double r, double *out) const
 // ---------------------------------------------------------------------------
 static double subpanel_r(const SubPanel &s, double x)
 {
-    if (s.c > 0.0) {
-        double u = 0.5 * (s.ua + s.ub) + 0.5 * (s.ua - s.ub) * x;   // x = +1 at r = ra
-        return s.c - u * u;
-    }
-    return 0.5 * (s.ra + s.rb) + 0.5 * (s.rb - s.ra) * x;
+    double v = 0.5 * (s.ua + s.ub) + 0.5 * (s.ua - s.ub) * x;   // sqrt variable: x = +1 at r = ra
+    return s.c > 0.0 ? s.c - v * v : v;
 }
 
 static void fit_subpanel(const LocalWeights &LW, const SubPanel &s, double *coef /* [nlev][D] */)
@@ -336,7 +333,11 @@ static SubPanel make_sub(double ra, double rb, double c)
     if (c > 0.0) {
         s.ua = std::sqrt(std::max(0.0, c - ra));
         s.ub = std::sqrt(std::max(0.0, c - rb));
+    } else {
+        s.ua = rb;   // linear variable: x = (2 r - ra - rb) / (rb - ra)
+        s.ub = ra;
     }
+    s.inv = 1.0 / (s.ua - s.ub);
     return s;
 }
 
@@ -349,6 +350,10 @@ LocalTable build_local_table(const LocalWeights &LW, int n_dy, double rel_tol)
     T.panel_base.assign(LW.W, 0);
     T.panel_l2n.assign(LW.W, 0);
     std::vector<double> coef, tmp((size_t)nl * D), ev(nl);
+    // Fit error is judged against max(scale of the panel, 1e-2 x scale of the
+    // largest weights): pairs near r = delta carry weights ~1e-5 of those at
+    // small r, so their absolute accuracy, not their relative one, matters.
+    double global_scale = 0.0;
     // regular panels k = 0..W-1: r in [max(k, 1/2) dt, (k+1) dt), sqrt variable about (k+1) dt
     for (int k = 0; k < LW.W; ++k) {
         double r0 = (k == 0 ? 0.5 : (double)k) * dt, r1 = (k + 1) * dt, c = (k + 1) * dt;
@@ -369,13 +374,15 @@ LocalTable build_local_table(const LocalWeights &LW, int n_dy, double rel_tol)
                     }
                 }
             }
-            if (err <= rel_tol * scale || l2n >= 5) {
+            global_scale = std::max(global_scale, scale);
+            const double ref = std::max(scale, 1e-2 * global_scale);
+            if (err <= rel_tol * ref || l2n >= 5) {
                 T.panel_base[k] = (int)T.subs.size();
                 T.panel_l2n[k] = l2n;
                 for (int s = 0; s < ns; ++s)
                     T.subs.push_back(make_sub(r0 + (r1 - r0) * s / ns, r0 + (r1 - r0) * (s + 1) / ns, c));
                 coef.insert(coef.end(), cf.begin(), cf.end());
-                T.max_err = std::max(T.max_err, scale > 0 ? err / scale : 0.0);
+                T.max_err = std::max(T.max_err, ref > 0 ? err / ref : 0.0);
                 break;
             }
         }
@@ -408,14 +415,8 @@ void local_table_eval(const LocalTable &T, double dt, int W, double r, double *o
         sub = T.dy_base + std::min(-e, T.n_dy) - 1;
     }
     const SubPanel &sp = T.subs[sub];
-    double xc;
-    if (sp.c > 0.0) {
-        const double u = std::sqrt(std::max(0.0, sp.c - r));
-        xc = (2.0 * u - sp.ua - sp.ub) / (sp.ua - sp.ub);
-    } else {
-        xc = (2.0 * r - sp.ra - sp.rb) / (sp.rb - sp.ra);
-    }
-    xc = std::min(1.0, std::max(-1.0, xc));
+    const double v = sp.c > 0.0 ? std::sqrt(std::max(0.0, sp.c - r)) : r;
+    const double xc = std::min(1.0, std::max(-1.0, (2.0 * v - sp.ua - sp.ub) * sp.inv));
     for (int d = 0; d < T.nlev; ++d) out[d] = cheb_eval(&T.coef[((size_t)sub * T.nlev + d) * kChebDeg], kChebDeg, xc);
 }
 
