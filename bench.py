@@ -57,8 +57,11 @@ def stage_costs(info: dict) -> dict:
         "fft_cols2": ("hbm", H * 2 * c + (R + 1) * Lp * 2 * c),
         "fft_rows2": ("hbm", (R + 1) * Lp * 2 * c + Lp * Lp * c),
         "interp": ("hbm", Lp * Lp * c + Nx * (8 + 2 * w * c + 8)),
-        # Clenshaw of degree 16 per level (2 flops x 16) + contraction (2 flops) per level and pair
-        "local": ("alu", info["n_local_pairs"] * nlev * (2 * info["cheb_degree"] + 2)),
+        # FP64 flops of the algorithm as executed: per source, the Chebyshev profile on every regular
+        # sub-panel (D coefficients, each a dot product over the sigma levels); per pair, one Clenshaw
+        # evaluation of degree D (2 flops per term) plus distance and sub-panel coordinate (~12 flops)
+        "local": ("alu", 2 * M * info["n_regular_subpanels"] * info["cheb_degree"] * nlev
+                  + info["n_local_pairs"] * (2 * info["cheb_degree"] + 12)),
         "combine": ("hbm", Nx * (8 + 8 + 4 + 8)),
     }
     return cost
@@ -75,7 +78,20 @@ def main():
                     help="targets of the CPU oracle sample (at the last timed step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="only run a device-to-device copy of this many GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_probe_gib > 0:
+        import torch
+        n = int(args.copy_probe_gib * 2**30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 8, "launches": 3}))
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding of the "

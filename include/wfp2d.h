@@ -95,6 +95,7 @@ typedef struct {
     int64_t steps_ingested;/* number of wfp2d_step calls so far */
     int64_t step_reported; /* n such that wfp2d_evaluate returns u(t_n) (<= 0: zero field) */
     int32_t precision;
+    int32_t n_regular_subpanels; /* local-weight sub-panels with r >= dt/2 */
 } wfp2d_info;
 
 /* Fill *opts with the defaults listed above.  Never fails for a valid pointer. */

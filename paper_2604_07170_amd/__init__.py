@@ -50,7 +50,7 @@ class Info(ctypes.Structure):
                    ("n_subpanels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32)]
                 + [(n, ctypes.c_int64) for n in ("M", "Nx", "n_local_pairs", "sigma_depth", "bytes_device",
                                                  "steps_ingested", "step_reported")]
-                + [("precision", ctypes.c_int32)])
+                + [("precision", ctypes.c_int32), ("n_regular_subpanels", ctypes.c_int32)])
 
 
 _lib = None

@@ -167,7 +167,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     const int64_t qmax = (p.precision == WFP2D_PREC_MIXED) ? 8192 : 4096;
     int64_t best_nf = -1;
     for (int P_ = 1; P_ <= 3; ++P_) {
-        int64_t Q = std::max<int64_t>(64, next_pow2((2 * N + P_ - 1) / P_));
+        int64_t Q = std::max<int64_t>(256, next_pow2((2 * N + P_ - 1) / P_));
         int64_t nf = P_ * Q;
         double gmax = p.dk * (double)nf / (2.0 * M_PI);
         int64_t lmin = (int64_t)std::ceil(-gmax - 0.5 * w);
@@ -412,6 +412,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     p.d_tgt_wts = upload_real(p, twts);
     p.d_grid = p.alloc<char>((int64_t)g.Lpad * g.Lpad * 2 * sr);
     p.d_T1 = p.alloc<char>((int64_t)g.Lpad * N * 2 * sr);
+    p.d_T1t = p.alloc<char>((int64_t)g.Lpad * N * 2 * sr);
     p.d_F = p.alloc<char>(N * N * 2 * sr);
     p.d_corr = upload_real(p, corr);
     p.d_tw = upload_real(p, tw);
@@ -442,6 +443,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_inj, inj);
     p.d_B = p.alloc<double2>(p.n_far * kNsoe);
     p.d_T2 = p.alloc<char>((R + 1) * (int64_t)g.Lpad * 2 * sr);
+    p.d_T2t = p.alloc<char>((R + 1) * (int64_t)g.Lpad * 2 * sr);
     p.d_cgrid = p.alloc<char>((int64_t)g.Lpad * g.Lpad * sr);
     p.d_uh = p.alloc<double>(Nx);
     p.d_ul = p.alloc<double>(Nx);
@@ -475,6 +477,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_panel_base, LT.panel_base);
     p.d_panel_l2n = p.alloc<int32_t>(p.W);
     upload(p.d_panel_l2n, LT.panel_l2n);
+    hip_check(fft_setup(p), "FFT kernel attributes");
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize after set-up");
 }
 
@@ -680,6 +683,7 @@ wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
     info->steps_ingested = p.steps;
     info->step_reported = p.steps - p.lookahead;
     info->precision = p.precision;
+    info->n_regular_subpanels = p.n_reg;
     return WFP2D_OK;
 }
 

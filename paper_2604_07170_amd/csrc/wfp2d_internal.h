@@ -54,6 +54,7 @@ struct Plan;
 // ---- launchers (kernels file) ----
 hipError_t launch_ingest(Plan &p, const double *sigma_in, int64_t slot);
 hipError_t launch_spread(Plan &p, int64_t slot_cur, int64_t slot_lag);
+hipError_t fft_setup(Plan &p);
 hipError_t launch_fft_rows1(Plan &p);
 hipError_t launch_fft_cols1(Plan &p);
 hipError_t launch_split(Plan &p, int64_t ring_cur, int64_t ring_lag);
@@ -109,6 +110,7 @@ struct Plan {
     int32_t *d_tile_off = nullptr, *d_tile_src = nullptr;
     void *d_grid = nullptr;           // [Lpad][Lpad] complex Real
     void *d_T1 = nullptr;             // [Lpad][N] complex Real (rows transformed)
+    void *d_T1t = nullptr;            // [N][Lpad] its transpose
     void *d_F = nullptr;              // [N][N] complex Real, index [nx+R][ny+R]
     void *d_corr = nullptr;           // [N] complex Real: e^{2 pi i n lmin/nf} / psi_hat(n)
     void *d_tw = nullptr;             // [nf] complex Real: e^{2 pi i j / nf}
@@ -129,6 +131,7 @@ struct Plan {
     double2 *d_B = nullptr;           // [n_far][640]
     // type 2
     void *d_T2 = nullptr;             // [R+1][Lpad] complex Real
+    void *d_T2t = nullptr;            // [Lpad][R+1] its transpose
     void *d_cgrid = nullptr;          // [Lpad][Lpad] Real
     int2 *d_tgt_base = nullptr;
     void *d_tgt_wts = nullptr;

@@ -92,11 +92,15 @@ __global__ __launch_bounds__(256) void k_spread(const double *__restrict__ sig_c
 }
 
 // ---------------------------------------------------------------------------
-// In-LDS Stockham FFT of length Q (power of two), radix 4 with a final radix-2
-// stage when log2 Q is odd.  sign = +1 computes sum x[m] e^{+2 pi i k m/Q},
-// sign = -1 the conjugate kernel.  Twiddles come from tw[j] = e^{2 pi i j/nf},
-// nf = P Q.  Returns the buffer that holds the result.
+// Line FFTs of length Q = 2^L (L >= 4) in one workgroup of T = Q/16 threads.
+// Each thread holds 16 values; Stockham passes of radix 16 run in registers
+// with one LDS exchange per pass, and a last pass of radix 2, 4 or 8 covers
+// L mod 4.  sign = +1 computes X[k] = sum_m x[m] e^{+2 pi i k m/Q}, sign = -1
+// the conjugate kernel.  Twiddles come from tw[j] = e^{2 pi i j/nf}, nf = P Q.
+// The LDS index is padded by one element every 16 against bank conflicts.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
 template <class C>
 __device__ __forceinline__ C twid(const C *__restrict__ tw, int idx, int sign)
 {
@@ -105,51 +109,144 @@ __device__ __forceinline__ C twid(const C *__restrict__ tw, int idx, int sign)
     return t;
 }
 
-template <class C>
-__device__ C *stockham(C *x, C *y, int Q, int sign, const C *__restrict__ tw, int P)
+// multiply by sign*i
+template <class C> __device__ __forceinline__ C mul_si(C a, int sign) { return sign > 0 ? C{-a.y, a.x} : C{a.y, -a.x}; }
+
+template <class C> __device__ __forceinline__ void dft2(C &a, C &b)
 {
-    int Ns = 1;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    while (Ns < Q) {
-        if (Q / Ns >= 4) {
-            const int nq = Q >> 2;
-            const int stride = (Q / (4 * Ns)) * P;
-            for (int j = tid; j < nq; j += nt) {
-                const int k = j % Ns;
-                C v0 = x[j], v1 = x[j + nq], v2 = x[j + 2 * nq], v3 = x[j + 3 * nq];
-                if (Ns > 1) {
-                    v1 = cmul(v1, twid(tw, k * stride, sign));
-                    v2 = cmul(v2, twid(tw, 2 * k * stride, sign));
-                    v3 = cmul(v3, twid(tw, 3 * k * stride, sign));
-                }
-                const C s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = csub(v1, v3);
-                const C wd = sign > 0 ? C{-d13.y, d13.x} : C{d13.y, -d13.x};
-                const int o = (j / Ns) * Ns * 4 + k;
-                y[o] = cadd(s02, s13);
-                y[o + Ns] = cadd(d02, wd);
-                y[o + 2 * Ns] = csub(s02, s13);
-                y[o + 3 * Ns] = csub(d02, wd);
-            }
-            Ns <<= 2;
-        } else {
-            const int nh = Q >> 1;
-            const int stride = (Q / (2 * Ns)) * P;
-            for (int j = tid; j < nh; j += nt) {
-                const int k = j % Ns;
-                C v0 = x[j], v1 = x[j + nh];
-                if (Ns > 1) v1 = cmul(v1, twid(tw, k * stride, sign));
-                const int o = (j / Ns) * Ns * 2 + k;
-                y[o] = cadd(v0, v1);
-                y[o + Ns] = csub(v0, v1);
-            }
-            Ns <<= 1;
-        }
-        __syncthreads();
-        C *t = x;
-        x = y;
-        y = t;
+    const C t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <class C> __device__ __forceinline__ void dft4(C &a, C &b, C &c, C &d, int sign)
+{
+    const C s02 = cadd(a, c), d02 = csub(a, c), s13 = cadd(b, d), d13 = mul_si(csub(b, d), sign);
+    a = cadd(s02, s13);
+    b = cadd(d02, d13);
+    c = csub(s02, s13);
+    d = csub(d02, d13);
+}
+
+// multiply by e^{sign 2 pi i m / 16}, m in [0, 16), with exact constants
+template <class C> __device__ __forceinline__ C rot16(C a, int m, int sign)
+{
+    using R = decltype(a.x);
+    const R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173), h = R(0.70710678118654752440);
+    R cr, ci;
+    switch (m & 15) {
+    case 0: return a;
+    case 1: cr = c1; ci = s1; break;
+    case 2: cr = h; ci = h; break;
+    case 3: cr = s1; ci = c1; break;
+    case 4: cr = 0; ci = 1; break;
+    case 5: cr = -s1; ci = c1; break;
+    case 6: cr = -h; ci = h; break;
+    case 7: cr = -c1; ci = s1; break;
+    case 8: cr = -1; ci = 0; break;
+    case 9: cr = -c1; ci = -s1; break;
+    default: cr = -h; ci = -h; break;   // m = 10 (largest used)
     }
-    return x;
+    if (sign < 0) ci = -ci;
+    return C{a.x * cr - a.y * ci, a.x * ci + a.y * cr};
+}
+
+template <class C> __device__ __forceinline__ void dft8(C *v, int sign)
+{
+    // even/odd split: X[k] = E[k] + w8^k O[k], X[k+4] = E[k] - w8^k O[k]
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3, sign);
+    dft4(o0, o1, o2, o3, sign);
+    o1 = rot16(o1, 2, sign);
+    o2 = rot16(o2, 4, sign);
+    o3 = rot16(o3, 6, sign);
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+template <class C> __device__ __forceinline__ void dft16(C *v, int sign)
+{
+    // n = 4 n1 + n2, k = k1 + 4 k2
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2], sign);
+    // now v[4 k1 + n2] = Y[n2][k1]; twiddle by w16^{n2 k1}
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+        for (int n2 = 1; n2 < 4; ++n2) v[4 * k1 + n2] = rot16(v[4 * k1 + n2], n2 * k1, sign);
+    C out[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C a = v[4 * k1], b = v[4 * k1 + 1], c = v[4 * k1 + 2], d = v[4 * k1 + 3];
+        dft4(a, b, c, d, sign);
+        out[k1] = a;
+        out[k1 + 4] = b;
+        out[k1 + 8] = c;
+        out[k1 + 12] = d;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = out[i];
+}
+
+// last Stockham pass of radix R in {2, 4, 8}: each thread does 16/R butterflies
+template <int R, class C>
+__device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int Ns, int sign, const C *__restrict__ tw, int P)
+{
+    constexpr int nb = 16 / R;
+    const int tid = threadIdx.x, T = Q >> 4, QR = Q / R;
+#pragma unroll
+    for (int i = 0; i < nb; ++i)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i * R + r] = lds[lpad(tid + T * i + r * QR)];
+    __syncthreads();
+    const int stride = (Q / (R * Ns)) * P;
+#pragma unroll
+    for (int i = 0; i < nb; ++i) {
+        const int j = tid + T * i, k = j % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], twid(tw, k * r * stride, sign));
+        if (R == 2) dft2(v[i * R], v[i * R + 1]);
+        else if (R == 4) dft4(v[i * R], v[i * R + 1], v[i * R + 2], v[i * R + 3], sign);
+        else dft8(v + i * R, sign);
+        const int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lpad(o + r * Ns)] = v[i * R + r];
+    }
+    __syncthreads();
+}
+
+// One workgroup transforms one line.  v[r] (r < 16) holds x[tid + r Q/16] on
+// entry; the result is left in lds (natural order, padded index).
+template <class C>
+__device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const C *__restrict__ tw, int P)
+{
+    const int tid = threadIdx.x, T = Q >> 4;
+    // first radix-16 pass (Ns = 1): no twiddles
+    dft16(v, sign);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[lpad(tid * 16 + r)] = v[r];
+    __syncthreads();
+    int Ns = 16, Lleft = L - 4;
+    while (Lleft >= 4) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = lds[lpad(tid + r * T)];
+        __syncthreads();
+        const int k = tid % Ns, stride = (Q / (16 * Ns)) * P;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twid(tw, k * r * stride, sign));
+        dft16(v, sign);
+        const int o = (tid / Ns) * Ns * 16 + k;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds[lpad(o + r * Ns)] = v[r];
+        __syncthreads();
+        Ns <<= 4;
+        Lleft -= 4;
+    }
+    if (Lleft == 1) tail_pass<2>(lds, v, Q, Ns, sign, tw, P);
+    else if (Lleft == 2) tail_pass<4>(lds, v, Q, Ns, sign, tw, P);
+    else if (Lleft == 3) tail_pass<8>(lds, v, Q, Ns, sign, tw, P);
 }
 
 // map sub-transform output k' of branch s to a signed mode n in [-R, R]; false if unused
@@ -161,76 +258,139 @@ __device__ __forceinline__ bool out_mode(int kp, int s, const Geom &g, int &n)
     return false;
 }
 
+__device__ __forceinline__ int ilog2(int q)
+{
+    int l = 0;
+    while ((1 << l) < q) ++l;
+    return l;
+}
+
 // ---------------------------------------------------------------------------
-// Type-1, first dimension: each band row -> modes n_x in [-R, R] (times the
-// x-direction correction e^{2 pi i n lmin/nf}/psi_hat(n)).  The length-nf
-// transform of a row that is zero outside its first Q entries is split into
-// P length-Q transforms of the twiddled row (nf = P Q).
+// Type-1 transform of one line (a band row, or a column after transposition):
+// x[m], m < Lpad (zero beyond), -> X(n) for n in [-R, R] times corr[n+R],
+// where the length-nf transform is split into P length-Q transforms of the
+// twiddled line (nf = P Q).  mode 0 writes out[n + R] for every n; mode 1
+// writes only the disk n_x^2 + n_y^2 <= Rd2 (n_x = line - R).
 // ---------------------------------------------------------------------------
-template <class R>
-__global__ __launch_bounds__(256) void k_rows1(const typename cplx<R>::T *__restrict__ grid, typename cplx<R>::T *__restrict__ T1,
-                                               const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
+template <class R, int MODE>
+__global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__restrict__ in, typename cplx<R>::T *__restrict__ out,
+                         const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
 {
     using C = typename cplx<R>::T;
-    constexpr int QM = qmax<R>();
-    constexpr int NPT = QM / 256;
-    __shared__ C bufA[QM];
-    __shared__ C bufB[QM];
-    const int row = blockIdx.x, tid = threadIdx.x;
-    C xin[NPT];
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int m = tid + 256 * i;
-        xin[i] = (m < g.Lpad) ? grid[(size_t)row * g.Lpad + m] : C{0, 0};
-    }
+    extern __shared__ char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int line = blockIdx.x, tid = threadIdx.x, T = g.Q >> 4, L = ilog2(g.Q);
+    const C *x = in + (size_t)line * g.Lpad;
+    C v[16];
+    const int nx = line - g.R;
     for (int s = 0; s < g.P; ++s) {
+        // the line is re-read for each branch (from L2) rather than held in registers
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int m = tid + 256 * i;
-            if (m < g.Q) bufA[m] = (m < g.Lpad) ? (s == 0 ? xin[i] : cmul(xin[i], tw[(s * m) % g.nf])) : C{0, 0};
+        for (int r = 0; r < 16; ++r) {
+            const int m = tid + r * T;
+            const C xm = m < g.Lpad ? x[m] : C{0, 0};
+            v[r] = s == 0 ? xm : cmul(xm, tw[(s * m) % g.nf]);
         }
-        __syncthreads();
-        C *res = stockham(bufA, bufB, g.Q, +1, tw, g.P);
-        for (int kp = tid; kp < g.Q; kp += 256) {
+        fft_line(lds, v, g.Q, L, +1, tw, g.P);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int kp = tid + i * T;
             int n;
-            if (out_mode(kp, s, g, n)) T1[(size_t)row * g.N + n + g.R] = cmul(res[kp], corr[n + g.R]);
+            if (!out_mode(kp, s, g, n)) continue;
+            if (MODE == 1 && (double)(nx * nx + n * n) > g.Rd2) continue;
+            out[(size_t)line * g.N + n + g.R] = cmul(lds[lpad(kp)], corr[n + g.R]);
         }
         __syncthreads();
     }
 }
 
-// Type-1, second dimension: each column n_x -> F(n_x, n_y) inside the disk.
-template <class R>
-__global__ __launch_bounds__(256) void k_cols1(const typename cplx<R>::T *__restrict__ T1, typename cplx<R>::T *__restrict__ F,
-                                               const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
+// ---------------------------------------------------------------------------
+// Type-2 transform of one line: input coefficients X(k) for k = n mod nf
+// (gathered by a functor), output y[m] = sum_k X(k) e^{-2 pi i k m/nf} for
+// m < Lpad, accumulated over the P branches.
+//   MODE 0 (columns): X from the packed half-disk coefficients of column n_x =
+//     line, times (2 or 1) conj(corr_x) conj(corr_y); output complex T2[line][m].
+//   MODE 1 (rows): X(k) = T2t[line][k] for k <= R; output Re y -> cgrid[line][m].
+// ---------------------------------------------------------------------------
+template <class R, int MODE>
+__global__ __launch_bounds__(512) void k_fft_t2(const typename cplx<R>::T *__restrict__ in, void *__restrict__ outv, const int32_t *__restrict__ col_off,
+                         const int32_t *__restrict__ col_ny0, const typename cplx<R>::T *__restrict__ corr,
+                         const typename cplx<R>::T *__restrict__ tw, Geom g)
 {
     using C = typename cplx<R>::T;
-    constexpr int QM = qmax<R>();
-    constexpr int NPT = QM / 256;
-    __shared__ C bufA[QM];
-    __shared__ C bufB[QM];
-    const int col = blockIdx.x, tid = threadIdx.x;
-    const int nx = col - g.R;
-    C xin[NPT];
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int m = tid + 256 * i;
-        xin[i] = (m < g.Lpad) ? T1[(size_t)m * g.N + col] : C{0, 0};
+    extern __shared__ char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int line = blockIdx.x, tid = threadIdx.x, T = g.Q >> 4, L = ilog2(g.Q);
+    int off = 0, cnt = 0, ny0 = 0;
+    C cx{1, 0};
+    if (MODE == 0) {
+        off = col_off[line];
+        cnt = col_off[line + 1] - off;
+        ny0 = col_ny0[line];
+        cx = cconj(corr[line + g.R]);
     }
+    C acc[16], v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = C{0, 0};
     for (int s = 0; s < g.P; ++s) {
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int m = tid + 256 * i;
-            if (m < g.Q) bufA[m] = (m < g.Lpad) ? (s == 0 ? xin[i] : cmul(xin[i], tw[(s * m) % g.nf])) : C{0, 0};
+        for (int r = 0; r < 16; ++r) {
+            const int kp = tid + r * T;
+            C val{0, 0};
+            if (MODE == 0) {
+                int ny;
+                if (out_mode(kp, s, g, ny) && ny >= ny0 && ny < ny0 + cnt) {
+                    const R fac = (line > 0 || ny > 0) ? R(2) : R(1);
+                    val = cmul(cmul(in[off + (ny - ny0)], cx), cconj(corr[ny + g.R]));
+                    val.x *= fac;
+                    val.y *= fac;
+                }
+            } else {
+                const int k = g.P * kp + s;
+                if (k <= g.R) val = in[(size_t)line * (g.R + 1) + k];
+            }
+            v[r] = val;
+        }
+        fft_line(lds, v, g.Q, L, -1, tw, g.P);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = tid + i * T;
+            if (m < g.Lpad) {
+                C r2 = lds[lpad(m)];
+                if (s > 0) r2 = cmul(r2, cconj(tw[(s * m) % g.nf]));
+                acc[i] = cadd(acc[i], r2);
+            }
         }
         __syncthreads();
-        C *res = stockham(bufA, bufB, g.Q, +1, tw, g.P);
-        for (int kp = tid; kp < g.Q; kp += 256) {
-            int ny;
-            if (out_mode(kp, s, g, ny) && (double)(nx * nx + ny * ny) <= g.Rd2)
-                F[(size_t)col * g.N + ny + g.R] = cmul(res[kp], corr[ny + g.R]);
-        }
-        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int m = tid + i * T;
+        if (m >= g.Lpad) continue;
+        if (MODE == 0) reinterpret_cast<C *>(outv)[(size_t)line * g.Lpad + m] = acc[i];
+        else reinterpret_cast<R *>(outv)[(size_t)line * g.Lpad + m] = acc[i].x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled transpose out[c][r] = in[r][c] of a rows x cols complex matrix.
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ __launch_bounds__(256) void k_transpose(const C *__restrict__ in, C *__restrict__ out, int rows, int cols)
+{
+    __shared__ C tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int j = 0; j < 32; j += 8) {
+        const int r = by + ty + j, c = bx + tx;
+        if (r < rows && c < cols) tile[ty + j][tx] = in[(size_t)r * cols + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 32; j += 8) {
+        const int c = bx + ty + j, r = by + tx;
+        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][ty + j];
     }
 }
 
@@ -383,99 +543,6 @@ __global__ __launch_bounds__(256) void k_far(const int32_t *__restrict__ far_pk,
 }
 
 // ---------------------------------------------------------------------------
-// Type-2, first dimension: for each column n_x >= 0 of the packed half disk,
-// b(n) = (2 or 1) a(n) conj(corr_x) conj(corr_y) -> c(n_x, m_y) for band rows.
-// u = Re sum_n b(n) e^{-i n.x}: Hermitian data is summed over one half plane
-// with doubled weights (the origin counted once).
-// ---------------------------------------------------------------------------
-template <class R>
-__global__ __launch_bounds__(256) void k_cols2(const typename cplx<R>::T *__restrict__ atot, const int32_t *__restrict__ col_off,
-                                               const int32_t *__restrict__ col_ny0, typename cplx<R>::T *__restrict__ T2,
-                                               const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
-{
-    using C = typename cplx<R>::T;
-    constexpr int QM = qmax<R>();
-    constexpr int NPT = QM / 256;
-    __shared__ C bufA[QM];
-    __shared__ C bufB[QM];
-    const int nx = blockIdx.x, tid = threadIdx.x;
-    const int off = col_off[nx], cnt = col_off[nx + 1] - off, ny0 = col_ny0[nx];
-    const C cx = cconj(corr[nx + g.R]);
-    C acc[NPT];
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) acc[i] = C{0, 0};
-    for (int s = 0; s < g.P; ++s) {
-        for (int kp = tid; kp < g.Q; kp += 256) {
-            int ny;
-            C v{0, 0};
-            if (out_mode(kp, s, g, ny) && ny >= ny0 && ny < ny0 + cnt) {
-                const R fac = (nx > 0 || ny > 0) ? R(2) : R(1);
-                const C a = atot[off + (ny - ny0)];
-                v = cmul(cmul(a, cx), cconj(corr[ny + g.R]));
-                v.x *= fac;
-                v.y *= fac;
-            }
-            bufA[kp] = v;
-        }
-        __syncthreads();
-        C *res = stockham(bufA, bufB, g.Q, -1, tw, g.P);
-#pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int m = tid + 256 * i;
-            if (m < g.Lpad) {
-                C r = res[m];
-                if (s > 0) r = cmul(r, cconj(tw[(s * m) % g.nf]));
-                acc[i] = cadd(acc[i], r);
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int m = tid + 256 * i;
-        if (m < g.Lpad) T2[(size_t)nx * g.Lpad + m] = acc[i];
-    }
-}
-
-// Type-2, second dimension: each band row m_y, modes n_x in [0, R] -> real grid.
-template <class R>
-__global__ __launch_bounds__(256) void k_rows2(const typename cplx<R>::T *__restrict__ T2, R *__restrict__ cgrid,
-                                               const typename cplx<R>::T *__restrict__ tw, Geom g)
-{
-    using C = typename cplx<R>::T;
-    constexpr int QM = qmax<R>();
-    constexpr int NPT = QM / 256;
-    __shared__ C bufA[QM];
-    __shared__ C bufB[QM];
-    const int row = blockIdx.x, tid = threadIdx.x;
-    C acc[NPT];
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) acc[i] = C{0, 0};
-    for (int s = 0; s < g.P; ++s) {
-        for (int kp = tid; kp < g.Q; kp += 256) {
-            const int k = g.P * kp + s;
-            bufA[kp] = (k <= g.R) ? T2[(size_t)k * g.Lpad + row] : C{0, 0};
-        }
-        __syncthreads();
-        C *res = stockham(bufA, bufB, g.Q, -1, tw, g.P);
-#pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int m = tid + 256 * i;
-            if (m < g.Lpad) {
-                C r = res[m];
-                if (s > 0) r = cmul(r, cconj(tw[(s * m) % g.nf]));
-                acc[i] = cadd(acc[i], r);
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int m = tid + 256 * i;
-        if (m < g.Lpad) cgrid[(size_t)row * g.Lpad + m] = acc[i].x;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Type-2 interpolation: one workgroup per tile stages the tile's grid region
 // (kTile + w - 1)^2 in LDS; each target of the tile sums w^2 products.
@@ -799,14 +866,41 @@ hipError_t launch_spread(Plan &p, int64_t slot_cur, int64_t slot_lag)
     return hipGetLastError();
 }
 
+static size_t fft_lds_bytes(const Plan &p) { return (size_t)(p.g.Q + p.g.Q / 16) * 2 * p.sizeof_real; }
+
+template <class R>
+static hipError_t fft_attrs(size_t bytes)
+{
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_fft_t1<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_fft_t1<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_fft_t2<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    return hipFuncSetAttribute((const void *)k_fft_t2<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t fft_setup(Plan &p)
+{
+    const size_t bytes = fft_lds_bytes(p);
+    return p.precision == WFP2D_PREC_MIXED ? fft_attrs<float>(bytes) : fft_attrs<double>(bytes);
+}
+
+template <class C>
+static void transpose(const Plan &p, const void *in, void *out, int rows, int cols)
+{
+    dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+    hipLaunchKernelGGL(k_transpose<C>, grid, dim3(256), 0, p.stream, (const C *)in, (C *)out, rows, cols);
+}
+
 hipError_t launch_fft_rows1(Plan &p)
 {
     const Geom &g = p.g;
+    const size_t sh = fft_lds_bytes(p);
+    const unsigned T = (unsigned)(g.Q / 16);
     if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_rows1<float>, dim3(g.Lpad), dim3(256), 0, p.stream, (const float2 *)p.d_grid, (float2 *)p.d_T1,
+        hipLaunchKernelGGL((k_fft_t1<float, 0>), dim3(g.Lpad), dim3(T), sh, p.stream, (const float2 *)p.d_grid, (float2 *)p.d_T1,
                            (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
     else
-        hipLaunchKernelGGL(k_rows1<double>, dim3(g.Lpad), dim3(256), 0, p.stream, (const double2 *)p.d_grid, (double2 *)p.d_T1,
+        hipLaunchKernelGGL((k_fft_t1<double, 0>), dim3(g.Lpad), dim3(T), sh, p.stream, (const double2 *)p.d_grid, (double2 *)p.d_T1,
                            (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
     return hipGetLastError();
 }
@@ -814,12 +908,17 @@ hipError_t launch_fft_rows1(Plan &p)
 hipError_t launch_fft_cols1(Plan &p)
 {
     const Geom &g = p.g;
-    if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_cols1<float>, dim3(g.N), dim3(256), 0, p.stream, (const float2 *)p.d_T1, (float2 *)p.d_F,
+    const size_t sh = fft_lds_bytes(p);
+    const unsigned T = (unsigned)(g.Q / 16);
+    if (p.precision == WFP2D_PREC_MIXED) {
+        transpose<float2>(p, p.d_T1, p.d_T1t, g.Lpad, g.N);
+        hipLaunchKernelGGL((k_fft_t1<float, 1>), dim3(g.N), dim3(T), sh, p.stream, (const float2 *)p.d_T1t, (float2 *)p.d_F,
                            (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
-    else
-        hipLaunchKernelGGL(k_cols1<double>, dim3(g.N), dim3(256), 0, p.stream, (const double2 *)p.d_T1, (double2 *)p.d_F,
+    } else {
+        transpose<double2>(p, p.d_T1, p.d_T1t, g.Lpad, g.N);
+        hipLaunchKernelGGL((k_fft_t1<double, 1>), dim3(g.N), dim3(T), sh, p.stream, (const double2 *)p.d_T1t, (double2 *)p.d_F,
                            (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
+    }
     return hipGetLastError();
 }
 
@@ -865,24 +964,31 @@ hipError_t launch_far(Plan &p, int64_t m)
 hipError_t launch_fft_cols2(Plan &p)
 {
     const Geom &g = p.g;
+    const size_t sh = fft_lds_bytes(p);
+    const unsigned T = (unsigned)(g.Q / 16);
     if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_cols2<float>, dim3(g.R + 1), dim3(256), 0, p.stream, (const float2 *)p.d_atot, p.d_col_off, p.d_col_ny0,
-                           (float2 *)p.d_T2, (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+        hipLaunchKernelGGL((k_fft_t2<float, 0>), dim3(g.R + 1), dim3(T), sh, p.stream, (const float2 *)p.d_atot, p.d_T2, p.d_col_off,
+                           p.d_col_ny0, (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
     else
-        hipLaunchKernelGGL(k_cols2<double>, dim3(g.R + 1), dim3(256), 0, p.stream, (const double2 *)p.d_atot, p.d_col_off, p.d_col_ny0,
-                           (double2 *)p.d_T2, (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
+        hipLaunchKernelGGL((k_fft_t2<double, 0>), dim3(g.R + 1), dim3(T), sh, p.stream, (const double2 *)p.d_atot, p.d_T2, p.d_col_off,
+                           p.d_col_ny0, (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
     return hipGetLastError();
 }
 
 hipError_t launch_fft_rows2(Plan &p)
 {
     const Geom &g = p.g;
-    if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_rows2<float>, dim3(g.Lpad), dim3(256), 0, p.stream, (const float2 *)p.d_T2, (float *)p.d_cgrid,
-                           (const float2 *)p.d_tw, g);
-    else
-        hipLaunchKernelGGL(k_rows2<double>, dim3(g.Lpad), dim3(256), 0, p.stream, (const double2 *)p.d_T2, (double *)p.d_cgrid,
-                           (const double2 *)p.d_tw, g);
+    const size_t sh = fft_lds_bytes(p);
+    const unsigned T = (unsigned)(g.Q / 16);
+    if (p.precision == WFP2D_PREC_MIXED) {
+        transpose<float2>(p, p.d_T2, p.d_T2t, g.R + 1, g.Lpad);
+        hipLaunchKernelGGL((k_fft_t2<float, 1>), dim3(g.Lpad), dim3(T), sh, p.stream, (const float2 *)p.d_T2t, p.d_cgrid, nullptr,
+                           nullptr, (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+    } else {
+        transpose<double2>(p, p.d_T2, p.d_T2t, g.R + 1, g.Lpad);
+        hipLaunchKernelGGL((k_fft_t2<double, 1>), dim3(g.Lpad), dim3(T), sh, p.stream, (const double2 *)p.d_T2t, p.d_cgrid, nullptr,
+                           nullptr, (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
+    }
     return hipGetLastError();
 }
 
