@@ -350,7 +350,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
 
     const int lev_min = -p.lookahead;
     LocalWeights LW(p.dt, p.W, p.p, lev_min, phi);
-    LocalTable LT = build_local_table(LW, 40, 1e-12);
+    LocalTable LT = build_local_table(LW, 40, 1e-11);
     g.nlev = LT.nlev;
     g.lev_min = lev_min;
     p.n_sub = (int32_t)LT.subs.size();
@@ -472,6 +472,9 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         if (nl > kLocalMaxLevels) fail(WFP2D_ERR_INFEASIBLE, "too many sigma levels for the local kernel (W + p too large)");
         p.local_sc = std::min<int>(kLocalMaxSrc, std::min(kLocalPsi / (p.n_reg * D), kLocalSig / nl));
         if (p.local_sc < 1) fail(WFP2D_ERR_INFEASIBLE, "local-weight tables too large for the local kernel");
+        bool one_sub = true;
+        for (int k = 0; k < p.W; ++k) one_sub = one_sub && LT.panel_l2n[k] == 0;
+        p.local_fast = one_sub && p.n_reg * D <= kFastRow && (nl == 35 || nl == 43);
     }
     p.d_panel_base = p.alloc<int32_t>(p.W);
     upload(p.d_panel_base, LT.panel_base);
@@ -831,7 +834,7 @@ wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, doubl
             if (what == 4) {
                 for (int64_t i = 0; i < k; ++i) LW.eta(in[5 + i], out + i * LW.nlev);
             } else {
-                LocalTable T = build_local_table(LW, 40, 1e-12);
+                LocalTable T = build_local_table(LW, 40, 1e-11);
                 for (int64_t i = 0; i < k; ++i) local_table_eval(T, dt, W, in[5 + i], out + i * LW.nlev);
             }
             break;
@@ -844,7 +847,7 @@ wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, doubl
             if (look < 0) look = (p + 1) / 2 - 1;
             Blend phi(W * dt, std::log(1.0 / tol), 160);
             LocalWeights LW(dt, W, p, -look, phi);
-            LocalTable T = build_local_table(LW, 40, 1e-12);
+            LocalTable T = build_local_table(LW, 40, 1e-11);
             need(4 + W);
             out[0] = (double)T.subs.size();
             out[1] = (double)T.dy_base;

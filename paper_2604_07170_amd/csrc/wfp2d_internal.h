@@ -15,7 +15,7 @@ namespace wfp2d {
 constexpr int kTile = 32;          // spreading / interpolation tile edge (fine-grid points)
 constexpr int kChunk = 256;        // modes per work chunk of the per-mode kernels
 constexpr int kNsoe = 640;         // SOE terms: 20 dyadic panels x 32 Gauss-Legendre nodes (Sec. 2.3)
-constexpr int kChebDeg = 24;       // Chebyshev terms per local-weight sub-panel
+constexpr int kChebDeg = 20;       // Chebyshev terms per local-weight sub-panel
 constexpr int kLocalThreads = 512; // local kernel: threads per workgroup (one target each)
 constexpr int kLocalPsi = 4096;    //   LDS doubles for the per-source Chebyshev profiles
 constexpr int kLocalSig = 640;     //   LDS doubles for the sources' sigma levels
@@ -23,6 +23,9 @@ constexpr int kLocalMaxSrc = 16;   //   sources per chunk (upper bound)
 constexpr int kLocalMaxLevels = 64;
 constexpr int kLocalQueue = 256;   //   queued pairs with r < dt/2 per chunk
 constexpr int kLocalOwn = 2;       //   targets owned per thread (regions up to 1024 targets in one pass)
+constexpr int kFastSrc = 16;       // fast local kernel: sources per chunk
+constexpr int kFastRow = 512;      //   max coefficient rows (regular sub-panels x Chebyshev terms)
+constexpr int kFastOwn = 4;        //   targets owned per thread
 
 // Work chunk of a per-mode kernel: modes [off, off+cnt) of packed column nx,
 // whose first mode has ny = ny0 (ny increases by one per mode).
@@ -146,6 +149,7 @@ struct Plan {
     double *d_cheb = nullptr;         // [n_sub][nlev][kChebDeg], scaled by 1/(2 pi)
     double *d_creg = nullptr;         // regular sub-panels [n_reg][kChebDeg][nlev], scaled by 1/(2 pi)
     int32_t n_reg = 0, local_sc = 1;  // regular sub-panels; sources per chunk in the local kernel
+    bool local_fast = false;          // one sub-panel per time-step panel and a supported level count
     int32_t *d_panel_base = nullptr;  // regular panel k -> first sub-panel, and log2 count
     int32_t *d_panel_l2n = nullptr;
     int32_t dy_base = 0, n_dy = 0;

@@ -9,6 +9,7 @@
 //   singular quadrature -> u = u_h + u_l in caller order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "wfp2d_internal.h"
@@ -604,6 +605,7 @@ struct LocalArgs {
     double *ul;
     int ncell, n_reg, dy_base, n_dy, sc;
     double delta, inv_dt;
+    double two_over_ua, two_over_ua0;   // 2/sqrt(dt), 2/sqrt(dt/2): Chebyshev coordinate of a panel
 };
 
 __device__ __forceinline__ double cheb_eval(const double *c, double x)
@@ -821,6 +823,151 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, int64_t m,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Local part, fast form (one sub-panel per time-step panel, NL sigma levels):
+// a persistent kernel in which thread e holds row e = (sub-panel P, Chebyshev
+// index c) of the coefficient table C_{P,c,d} in registers for its lifetime,
+// so the per-source profile coefficients psi_{j,P,c} = sum_d C_{P,c,d} sigma_{j,d}
+// of every source cell need only sigma from LDS.  The sub-panel of a pair is
+// its time-step panel k = floor(r/dt) and the Chebyshev coordinate is
+// x = 2 sqrt((k+1) dt - r) / u_a - 1, both computed arithmetically.
+// ---------------------------------------------------------------------------
+template <int NL>
+__global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, int64_t m, Geom g)
+{
+    __shared__ double psi[kFastSrc * kFastRow];   // [source][row]
+    __shared__ double sigs[kFastSrc * NL];
+    __shared__ double2 spos[kFastSrc];
+    __shared__ int qs[kLocalQueue], qt[kLocalQueue];
+    __shared__ double qr[kLocalQueue];
+    __shared__ int qn;
+    __shared__ int rbeg[5], rcum[6];
+
+    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = bd >> 6;
+    const int n = A.ncell, D = kChebDeg, nrow = A.n_reg * kChebDeg;
+    const double d2 = A.delta * A.delta, dt = g.dt;
+    double cr[NL];
+#pragma unroll
+    for (int d = 0; d < NL; ++d) cr[d] = tid < nrow ? A.creg[(size_t)tid * NL + d] : 0.0;
+
+    for (int cell = blockIdx.x; cell < n * n; cell += gridDim.x) {
+        const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
+        if (s0 == s1) continue;                     // uniform across the workgroup
+        const int cx = cell % n, cy = cell / n;
+        if (tid == 0) {
+            int cum = 0, r = 0;
+            const int xa = max(0, cx - 2), xb = min(n - 1, cx + 2);
+            for (int yy = max(0, cy - 2); yy <= min(n - 1, cy + 2); ++yy, ++r) {
+                const int b = A.tcell_start[yy * n + xa], e = A.tcell_start[yy * n + xb + 1];
+                rbeg[r] = b;
+                rcum[r] = cum;
+                cum += e - b;
+            }
+            for (; r < 5; ++r) {
+                rbeg[r] = 0;
+                rcum[r] = cum;
+            }
+            rcum[5] = cum;
+        }
+        __syncthreads();
+        const int NT = rcum[5];
+        for (int tc0 = 0; tc0 < NT; tc0 += kFastOwn * bd) {
+            const int nown = min(kFastOwn, (NT - tc0 + bd - 1) / bd);
+            int tg[kFastOwn];
+            double2 x[kFastOwn];
+            double acc[kFastOwn];
+#pragma unroll
+            for (int j = 0; j < kFastOwn; ++j) {
+                const int kk = tc0 + tid + j * bd;
+                tg[j] = -1;
+                x[j] = make_double2(1e30, 1e30);
+                acc[j] = 0.0;
+                if (j < nown && kk < NT) {
+                    int r = 0;
+                    while (r < 4 && kk >= rcum[r + 1]) ++r;
+                    tg[j] = rbeg[r] + (kk - rcum[r]);
+                    x[j] = A.txy[tg[j]];
+                }
+            }
+            for (int sb = s0; sb < s1; sb += kFastSrc) {
+                const int ns = min(kFastSrc, s1 - sb);
+                for (int e = tid; e < ns * NL; e += bd) {
+                    const int sidx = e / NL, d = e - sidx * NL;
+                    sigs[e] = A.sig[sig_slot(m, d, g) * g.M + sb + sidx];
+                }
+                if (tid < ns) spos[tid] = A.sxy[sb + tid];
+                if (tid == 0) qn = 0;
+                __syncthreads();
+                if (tid < nrow) {
+                    for (int q = 0; q < ns; ++q) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int d = 0; d < NL; ++d) v = fma(cr[d], sigs[q * NL + d], v);
+                        psi[q * nrow + tid] = v;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < kFastOwn; ++j) {
+                    if (j >= nown) continue;
+                    const double2 xj = x[j];
+                    for (int sidx = 0; sidx < ns; sidx += 2) {
+                        const bool two = sidx + 1 < ns;
+                        const int s2 = two ? sidx + 1 : sidx;
+                        const double2 y0 = spos[sidx], y1 = spos[s2];
+                        const double ax = xj.x - y0.x, ay = xj.y - y0.y, bx = xj.x - y1.x, by = xj.y - y1.y;
+                        const double ra2 = ax * ax + ay * ay, rb2 = bx * bx + by * by;
+                        bool ha = ra2 > 0.0 && ra2 < d2, hb = two && rb2 > 0.0 && rb2 < d2;
+                        if (!(ha || hb)) continue;
+                        const double ra = sqrt(ra2), rb = sqrt(rb2);
+                        const double rra = ra * A.inv_dt, rrb = rb * A.inv_dt;
+                        if ((ha && rra < 0.5) || (hb && rrb < 0.5)) {   // rare: queue, evaluated level by level
+                            const bool qa = ha && rra < 0.5, qb = hb && rrb < 0.5;
+                            int qq = atomicAdd(&qn, (qa ? 1 : 0) + (qb ? 1 : 0));
+                            if (qa) {
+                                if (qq < kLocalQueue) { qs[qq] = sidx; qt[qq] = tg[j]; qr[qq] = ra; }
+                                else acc[j] += dyadic_direct(A, sigs + sidx * NL, NL, ra, rra);
+                                ++qq;
+                                ha = false;
+                            }
+                            if (qb) {
+                                if (qq < kLocalQueue) { qs[qq] = s2; qt[qq] = tg[j]; qr[qq] = rb; }
+                                else acc[j] += dyadic_direct(A, sigs + s2 * NL, NL, rb, rrb);
+                                hb = false;
+                            }
+                            if (!(ha || hb)) continue;
+                        }
+                        const int ka = min((int)rra, g.W - 1), kb = min((int)rrb, g.W - 1);
+                        const double xa = ha ? fmin(1.0, fmax(-1.0, sqrt(fmax(0.0, (ka + 1) * dt - ra)) * (ka ? A.two_over_ua : A.two_over_ua0) - 1.0)) : 0.0;
+                        const double xb = hb ? fmin(1.0, fmax(-1.0, sqrt(fmax(0.0, (kb + 1) * dt - rb)) * (kb ? A.two_over_ua : A.two_over_ua0) - 1.0)) : 0.0;
+                        double va, vb;
+                        cheb_eval2(psi + sidx * nrow + (ha ? ka : 0) * D, xa, psi + s2 * nrow + (hb ? kb : 0) * D, xb, va, vb);
+                        acc[j] += (ha ? va : 0.0) + (hb ? vb : 0.0);
+                    }
+                }
+                __syncthreads();
+                const int nq = min(qn, kLocalQueue);
+                for (int q = wave; q < nq; q += nwave) {
+                    const int sidx = qs[q];
+                    const double r = qr[q];
+                    const int sub = dyadic_sub(A, r * A.inv_dt);
+                    const double xc = sub_coord(A.subs[sub], r);
+                    double v = 0.0;
+                    for (int d = lane; d < NL; d += 64)
+                        v = fma(cheb_eval(A.cheb + ((size_t)sub * NL + d) * D, xc), sigs[sidx * NL + d], v);
+                    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                    if (lane == 0) unsafeAtomicAdd(&A.ul[qt[q]], v);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int j = 0; j < kFastOwn; ++j)
+                if (tg[j] >= 0 && acc[j] != 0.0) unsafeAtomicAdd(&A.ul[tg[j]], acc[j]);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_zero_f64(double *__restrict__ p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1026,6 +1173,19 @@ hipError_t launch_local(Plan &p, int64_t m)
     A.sc = p.local_sc;
     A.delta = p.delta;
     A.inv_dt = 1.0 / p.dt;
+    A.two_over_ua = 2.0 / sqrt(p.dt);
+    A.two_over_ua0 = 2.0 / sqrt(0.5 * p.dt);
+    if (p.local_fast) {
+        const int nrow = p.n_reg * kChebDeg;
+        const unsigned threads = (unsigned)((nrow + 63) / 64 * 64);
+        const int cells = p.ncell * p.ncell;
+        const unsigned grid = (unsigned)std::min(cells, 2 * 256);
+        if (p.g.nlev == 35)
+            hipLaunchKernelGGL(k_local_fast<35>, dim3(grid), dim3(threads), 0, p.stream, A, m, p.g);
+        else
+            hipLaunchKernelGGL(k_local_fast<43>, dim3(grid), dim3(threads), 0, p.stream, A, m, p.g);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_local, dim3((unsigned)(p.ncell * p.ncell)), dim3(kLocalThreads), 0, p.stream, A, m, p.g);
     return hipGetLastError();
 }
