@@ -165,6 +165,35 @@ const char *wfp2d_last_error(wfp2d_plan plan);
 wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t *bytes);
 
 /*
+ * Graph replay of one plan.  wfp2d_graph_capture records one step followed by
+ * one evaluation into a HIP graph, reading the samples from the fixed device
+ * pointer sigma [M] and writing u into the fixed device pointer u [Nx]
+ * (both borrowed for the graph's lifetime); wfp2d_graph_launch replays it on
+ * the plan's stream, equivalent to wfp2d_step(sigma) + wfp2d_evaluate(u).
+ * The caller writes sigma_j(t_n) into sigma before each launch.  Capturing
+ * again replaces the graph.  Not allowed while stage timing is enabled.
+ * Errors: ERR_ARG, ERR_STATE, ERR_DEVICE.
+ */
+wfp2d_status wfp2d_graph_capture(wfp2d_plan plan, const double *sigma, double *u);
+wfp2d_status wfp2d_graph_launch(wfp2d_plan plan);
+
+/*
+ * Batches of independent scatterers: n plans on one device advanced together
+ * by one graph launch per step.  sigma[i] / u[i] are fixed device pointers of
+ * plan i (as for wfp2d_graph_capture); stream is the (non-default) hipStream_t
+ * the batch is launched on.  The plans' work is captured on n_streams
+ * forked capture streams (>= 1), so different plans may run concurrently.
+ * The plans must outlive the batch and must not be stepped otherwise while
+ * it is in use.  Errors (message via wfp2d_last_error(NULL)): ERR_ARG, ERR_STATE,
+ * ERR_DEVICE, ERR_NOMEM.
+ */
+typedef struct wfp2d_batch_s *wfp2d_batch;
+wfp2d_status wfp2d_batch_create(wfp2d_batch *out, int32_t n, const wfp2d_plan *plans, const double *const *sigma,
+                                double *const *u, int32_t n_streams, void *stream);
+wfp2d_status wfp2d_batch_launch(wfp2d_batch batch);
+wfp2d_status wfp2d_batch_destroy(wfp2d_batch batch);
+
+/*
  * Per-stage timing with HIP events recorded on the plan's stream around every
  * launch of the hot path (for measurement; adds one event pair per launch).
  * wfp2d_set_timing(plan, 1) clears and enables the accumulators, 0 disables.

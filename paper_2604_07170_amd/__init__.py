@@ -78,8 +78,15 @@ def load_library():
     lib.wfp2d_host_eval.argtypes = [i32, dp, i64, dp, i64, ctypes.POINTER(i64)]
     lib.wfp2d_set_timing.argtypes = [vp, i32]
     lib.wfp2d_get_timing.argtypes = [vp, dp, ctypes.POINTER(i64), i32]
+    lib.wfp2d_graph_capture.argtypes = [vp, vp, vp]
+    lib.wfp2d_graph_launch.argtypes = [vp]
+    lib.wfp2d_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), i32, vp]
+    lib.wfp2d_batch_launch.argtypes = [vp]
+    lib.wfp2d_batch_destroy.argtypes = [vp]
     for f in ("wfp2d_default_opts", "wfp2d_init", "wfp2d_step", "wfp2d_evaluate", "wfp2d_query", "wfp2d_destroy",
-              "wfp2d_debug_copy", "wfp2d_host_eval", "wfp2d_set_timing", "wfp2d_get_timing"):
+              "wfp2d_debug_copy", "wfp2d_host_eval", "wfp2d_set_timing", "wfp2d_get_timing", "wfp2d_graph_capture",
+              "wfp2d_graph_launch", "wfp2d_batch_create", "wfp2d_batch_launch", "wfp2d_batch_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -182,6 +189,22 @@ class Wfp2d:
         self._check(self.lib.wfp2d_evaluate(self.h, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    # -- graph replay --
+    def graph_capture(self, sigma, u):
+        """Record one step (reading `sigma`) + evaluation (writing `u`) into a graph; the
+        tensors are borrowed until the plan is closed or captured again."""
+        t = self._torch
+        for x, n in ((sigma, self.M), (u, self.Nx)):
+            if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == t.float64 and x.numel() == n
+                    and x.is_contiguous()):
+                raise ValueError("graph buffers must be contiguous float64 CUDA tensors of size M / Nx")
+        self._graph_keep = (sigma, u)
+        self._check(self.lib.wfp2d_graph_capture(self.h, ctypes.c_void_p(sigma.data_ptr()),
+                                                 ctypes.c_void_p(u.data_ptr())))
+
+    def graph_launch(self):
+        self._check(self.lib.wfp2d_graph_launch(self.h))
+
     STAGES = ("ingest", "spread", "fft_rows1", "fft_cols1", "split", "near", "far", "fft_cols2", "fft_rows2",
               "interp", "local", "combine")
     KERNELS = ("k_ingest", "k_spread", "k_rows1", "k_cols1", "k_split", "k_near", "k_far", "k_cols2", "k_rows2",
@@ -214,8 +237,56 @@ class Wfp2d:
         return buf
 
     def close(self):
+        self._graph_keep = None
         if getattr(self, "h", None):
             self.lib.wfp2d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent plans advanced together: one graph launch per step.
+
+    sigma[i] / u[i] are fixed float64 CUDA tensors of plan i (M_i / Nx_i elements);
+    the caller fills sigma[i] with sigma_j(t_n) before each launch and reads u[i]
+    (u at t_{n - lookahead_i}) after it."""
+
+    def __init__(self, plans, sigma, u, n_streams: int = 4, stream=None):
+        import torch
+        self.lib = load_library()
+        n = len(plans)
+        if not (n == len(sigma) == len(u)) or n == 0:
+            raise ValueError("plans, sigma and u must be non-empty lists of equal length")
+        for p, s, x in zip(plans, sigma, u):
+            for tsr, m in ((s, p.M), (x, p.Nx)):
+                if not (isinstance(tsr, torch.Tensor) and tsr.is_cuda and tsr.dtype == torch.float64
+                        and tsr.numel() == m and tsr.is_contiguous()):
+                    raise ValueError("batch buffers must be contiguous float64 CUDA tensors of size M_i / Nx_i")
+        if stream is None:
+            stream = torch.cuda.current_stream(plans[0].device)
+        self.plans, self.sigma, self.u, self.stream = list(plans), list(sigma), list(u), stream
+        arr = lambda xs: (ctypes.c_void_p * n)(*[ctypes.c_void_p(x) for x in xs])
+        h = ctypes.c_void_p()
+        rc = self.lib.wfp2d_batch_create(ctypes.byref(h), n, arr([p.h.value for p in plans]),
+                                         arr([s.data_ptr() for s in sigma]), arr([x.data_ptr() for x in u]),
+                                         int(n_streams), ctypes.c_void_p(int(stream.cuda_stream)))
+        if rc != 0:
+            raise Wfp2dError(rc, self.lib.wfp2d_last_error(None).decode())
+        self.h = h
+
+    def launch(self):
+        rc = self.lib.wfp2d_batch_launch(self.h)
+        if rc != 0:
+            raise Wfp2dError(rc, self.lib.wfp2d_last_error(None).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.wfp2d_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

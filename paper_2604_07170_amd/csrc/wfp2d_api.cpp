@@ -51,6 +51,8 @@ Plan::~Plan()
     if (stream) (void)hipStreamSynchronize(stream);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
     for (void *ptr : allocs) (void)hipFree(ptr);
 }
 
@@ -395,6 +397,8 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
 
     // ---------------- device memory ----------------
     const int64_t sr = p.sizeof_real;
+    g.lookahead = p.lookahead;
+    p.d_step = p.alloc<int64_t>(1);
     p.d_sig = p.alloc<double>(g.sig_depth * M);
     p.d_src_perm = p.alloc<int32_t>(M);
     upload(p.d_src_perm, sperm);
@@ -484,43 +488,90 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize after set-up");
 }
 
-static void do_step(Plan &p, const double *sigma)
+// One step: a fixed sequence of launches whose arguments do not depend on the
+// step index (the kernels read the device-resident step counter), so the
+// sequence can also be captured in a graph.
+static void enqueue_step(Plan &p, const double *sigma)
 {
-    hip_check(hipSetDevice(p.device), "hipSetDevice");
-    const Geom &g = p.g;
-    p.steps += 1;
-    const int64_t slot = p.steps % g.sig_depth;
-    timed(p, 0, "ingest", [&] { return launch_ingest(p, sigma, slot); });
-    const int64_t m = p.steps - p.lookahead;
-    if (m < 1) return;
-    auto md = [](int64_t a, int64_t b) { return ((a % b) + b) % b; };
-    timed(p, 1, "spread", [&] { return launch_spread(p, md(m, g.sig_depth), md(m - p.LA, g.sig_depth)); });
+    timed(p, 0, "ingest", [&] {
+        hipError_t e = launch_step_begin(p);
+        return e != hipSuccess ? e : launch_ingest(p, sigma);
+    });
+    timed(p, 1, "spread", [&] { return launch_spread(p); });
     timed(p, 2, "fft rows (type 1)", [&] { return launch_fft_rows1(p); });
     timed(p, 3, "fft columns (type 1)", [&] { return launch_fft_cols1(p); });
-    timed(p, 4, "hermitian split", [&] { return launch_split(p, md(m, p.W), md(m - p.LA, p.W)); });
-    timed(p, 5, "near-history update", [&] { return launch_near(p, m); });
-    timed(p, 6, "far-history update", [&] { return launch_far(p, m); });
+    timed(p, 4, "hermitian split", [&] { return launch_split(p); });
+    timed(p, 5, "near-history update", [&] { return launch_near(p); });
+    timed(p, 6, "far-history update", [&] { return launch_far(p); });
 }
 
-static void do_evaluate(Plan &p, double *u)
+static void enqueue_evaluate(Plan &p, double *u)
 {
-    hip_check(hipSetDevice(p.device), "hipSetDevice");
-    const int64_t m = p.steps - p.lookahead;
-    if (m < 1) {
-        timed(p, 11, "combine", [&] { return launch_combine(p, u, 1); });
-        return;
-    }
     timed(p, 7, "fft columns (type 2)", [&] { return launch_fft_cols2(p); });
     timed(p, 8, "fft rows (type 2)", [&] { return launch_fft_rows2(p); });
     timed(p, 9, "interpolation", [&] { return launch_interp(p); });
     timed(p, 10, "local part", [&] {
         hipError_t e = launch_zero_f64(p, p.d_ul, p.Nx);
-        return e != hipSuccess ? e : launch_local(p, m);
+        return e != hipSuccess ? e : launch_local(p);
     });
-    timed(p, 11, "combine", [&] { return launch_combine(p, u, 0); });
+    timed(p, 11, "combine", [&] { return launch_combine(p, u); });
+}
+
+static void do_step(Plan &p, const double *sigma)
+{
+    hip_check(hipSetDevice(p.device), "hipSetDevice");
+    p.steps += 1;
+    enqueue_step(p, sigma);
+}
+
+static void do_evaluate(Plan &p, double *u)
+{
+    hip_check(hipSetDevice(p.device), "hipSetDevice");
+    enqueue_evaluate(p, u);
+}
+
+// capture `body` (which enqueues on `st`) into an executable graph
+template <class F>
+static void capture_graph(hipStream_t st, hipGraph_t &graph, hipGraphExec_t &exec, F &&body)
+{
+    if (exec) {
+        (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
+    if (graph) {
+        (void)hipGraphDestroy(graph);
+        graph = nullptr;
+    }
+    hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        body();
+    } catch (...) {
+        hipGraph_t g0 = nullptr;
+        (void)hipStreamEndCapture(st, &g0);
+        if (g0) (void)hipGraphDestroy(g0);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+    hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
 }
 
 }  // namespace wfp2d
+
+struct wfp2d_batch_s {
+    std::vector<wfp2d_plan> plans;
+    hipStream_t stream = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> events;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~wfp2d_batch_s()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipStream_t s : side) (void)hipStreamDestroy(s);
+    }
+};
 
 using namespace wfp2d;
 
@@ -750,6 +801,124 @@ wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t 
         hip_check(hipMemcpy(dst, src, n, hipMemcpyDeviceToHost), "copy");
         *bytes = n;
     });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_graph_capture(wfp2d_plan plan, const double *sigma, double *u)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        if (!sigma || !u) fail(WFP2D_ERR_ARG, "NULL pointer");
+        if (p.timing) fail(WFP2D_ERR_STATE, "stage timing is enabled");
+        if (!p.stream) fail(WFP2D_ERR_STATE, "graph capture needs a non-default stream");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        capture_graph(p.stream, p.graph, p.graph_exec, [&] {
+            enqueue_step(p, sigma);
+            enqueue_evaluate(p, u);
+        });
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_graph_launch(wfp2d_plan plan)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        if (!p.graph_exec) fail(WFP2D_ERR_STATE, "no graph captured");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        hip_check(hipGraphLaunch(p.graph_exec, p.stream), "hipGraphLaunch");
+        p.steps += 1;
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_batch_create(wfp2d_batch *out, int32_t n, const wfp2d_plan *plans, const double *const *sigma,
+                                double *const *u, int32_t n_streams, void *stream)
+{
+    if (out) *out = nullptr;
+    wfp2d_batch_s *b = nullptr;
+    try {
+        if (!out || n <= 0 || !plans || !sigma || !u) fail(WFP2D_ERR_ARG, "bad batch arguments");
+        const int dev = plans[0] ? plans[0]->p.device : 0;
+        for (int i = 0; i < n; ++i) {
+            if (!plans[i] || !sigma[i] || !u[i]) fail(WFP2D_ERR_ARG, "NULL plan or pointer in batch");
+            if (plans[i]->p.device != dev) fail(WFP2D_ERR_ARG, "batch plans must share a device");
+            if (plans[i]->p.timing) fail(WFP2D_ERR_STATE, "stage timing is enabled on a batch plan");
+        }
+        if (!stream) fail(WFP2D_ERR_ARG, "a batch needs a non-default stream");
+        b = new wfp2d_batch_s();
+        b->plans.assign(plans, plans + n);
+        b->stream = (hipStream_t)stream;
+        hip_check(hipSetDevice(dev), "hipSetDevice");
+        const int ns = std::max(1, std::min<int>(n_streams, n));
+        std::vector<hipStream_t> cap(ns);
+        for (int k = 0; k < ns; ++k) {
+            hipStream_t s;
+            hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+            b->side.push_back(s);
+            cap[k] = s;
+        }
+        for (int k = 0; k < 2 * ns + 1; ++k) {
+            hipEvent_t e;
+            hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+            b->events.push_back(e);
+        }
+        // plans are re-pointed at the capture streams while recording
+        std::vector<hipStream_t> saved(n);
+        for (int i = 0; i < n; ++i) saved[i] = plans[i]->p.stream;
+        try {
+            capture_graph(b->stream, b->graph, b->exec, [&] {
+                hip_check(hipEventRecord(b->events[0], b->stream), "hipEventRecord");
+                for (int k = 0; k < ns; ++k) hip_check(hipStreamWaitEvent(cap[k], b->events[0], 0), "hipStreamWaitEvent");
+                for (int i = 0; i < n; ++i) {
+                    Plan &p = plans[i]->p;
+                    p.stream = cap[i % ns];
+                    enqueue_step(p, sigma[i]);
+                    enqueue_evaluate(p, u[i]);
+                }
+                for (int k = 0; k < ns; ++k) {
+                    hip_check(hipEventRecord(b->events[1 + k], cap[k]), "hipEventRecord");
+                    hip_check(hipStreamWaitEvent(b->stream, b->events[1 + k], 0), "hipStreamWaitEvent");
+                }
+            });
+        } catch (...) {
+            for (int i = 0; i < n; ++i) plans[i]->p.stream = saved[i];
+            throw;
+        }
+        for (int i = 0; i < n; ++i) plans[i]->p.stream = saved[i];
+        *out = b;
+        return WFP2D_OK;
+    } catch (const Failure &f) {
+        g_init_error = f.msg;
+        delete b;
+        return f.code;
+    } catch (const std::exception &e) {
+        g_init_error = e.what();
+        delete b;
+        return WFP2D_ERR_DEVICE;
+    }
+}
+
+wfp2d_status wfp2d_batch_launch(wfp2d_batch b)
+{
+    if (!b || !b->exec) return WFP2D_ERR_STATE;
+    try {
+        hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+        for (wfp2d_plan pl : b->plans) pl->p.steps += 1;
+        return WFP2D_OK;
+    } catch (const Failure &f) {
+        g_init_error = f.msg;
+        return f.code;
+    }
+}
+
+wfp2d_status wfp2d_batch_destroy(wfp2d_batch b)
+{
+    if (!b) return WFP2D_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
     return WFP2D_OK;
 }
 

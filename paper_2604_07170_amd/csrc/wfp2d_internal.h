@@ -45,6 +45,7 @@ struct SubPanel {
 struct Geom {
     int64_t M, Nx;
     int32_t W, LA, nlev, lev_min;      // levels d in [lev_min, lev_min + nlev)
+    int32_t lookahead;                 // reported step m = ingested step n - lookahead
     int64_t sig_depth;                 // sigma ring slots
     double dt, dk, K, Kf, Kmax, Rd2;   // Rd2 = (Kmax/dk)^2
     int32_t R, N;                      // N = 2R + 1
@@ -55,20 +56,21 @@ struct Geom {
 struct Plan;
 
 // ---- launchers (kernels file) ----
-hipError_t launch_ingest(Plan &p, const double *sigma_in, int64_t slot);
-hipError_t launch_spread(Plan &p, int64_t slot_cur, int64_t slot_lag);
+hipError_t launch_step_begin(Plan &p);
+hipError_t launch_ingest(Plan &p, const double *sigma_in);
+hipError_t launch_spread(Plan &p);
 hipError_t fft_setup(Plan &p);
 hipError_t launch_fft_rows1(Plan &p);
 hipError_t launch_fft_cols1(Plan &p);
-hipError_t launch_split(Plan &p, int64_t ring_cur, int64_t ring_lag);
-hipError_t launch_near(Plan &p, int64_t m);
-hipError_t launch_far(Plan &p, int64_t m);
+hipError_t launch_split(Plan &p);
+hipError_t launch_near(Plan &p);
+hipError_t launch_far(Plan &p);
 hipError_t launch_fft_cols2(Plan &p);
 hipError_t launch_fft_rows2(Plan &p);
 hipError_t launch_interp(Plan &p);
-hipError_t launch_local(Plan &p, int64_t m);
+hipError_t launch_local(Plan &p);
 hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n);
-hipError_t launch_combine(Plan &p, double *u_out, int zero);
+hipError_t launch_combine(Plan &p, double *u_out);
 hipError_t launch_zero(Plan &p, void *ptr, int64_t bytes);
 
 // ---- the plan ----
@@ -103,6 +105,7 @@ struct Plan {
     // ---- device memory ----
     std::vector<void *> allocs;
     int64_t bytes_device = 0;
+    int64_t *d_step = nullptr;        // device-resident count of ingested steps
     double *d_sig = nullptr;          // [sig_depth][M] float64, sorted source order
     int32_t *d_src_perm = nullptr;    // sorted j -> caller index
     int32_t *d_tgt_rank = nullptr;    // caller index -> sorted i
@@ -155,6 +158,10 @@ struct Plan {
     int32_t dy_base = 0, n_dy = 0;
 
     std::string err;
+
+    // graph replay of one step + evaluation
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 
     // stage timing (events recorded around launches when enabled)
     static constexpr int kStages = 12;

@@ -36,12 +36,21 @@ template <> __device__ __forceinline__ double2 from_d<double2>(double2 a) { retu
 template <class R> constexpr int qmax() { return sizeof(R) == 4 ? 8192 : 4096; }
 
 // ---------------------------------------------------------------------------
-// sigma ingest: ring slot <- caller's samples gathered into sorted order
+// The step counter lives in device memory so that one step is a fixed
+// sequence of launches with fixed arguments (capturable in a graph):
+// k_step_begin advances it; every later kernel derives the ingested step n,
+// the reported step m = n - lookahead and its ring slots from it.
 // ---------------------------------------------------------------------------
-__global__ void k_ingest(const double *__restrict__ in, const int32_t *__restrict__ perm, double *__restrict__ out, int64_t M)
+__device__ __forceinline__ int64_t pmod(int64_t a, int64_t b) { return ((a % b) + b) % b; }
+
+__global__ void k_step_begin(int64_t *step) { step[0] += 1; }
+
+// sigma ingest: ring slot of step n <- caller's samples gathered into sorted order
+__global__ void k_ingest(const double *__restrict__ in, const int32_t *__restrict__ perm, double *__restrict__ sig, int64_t M,
+                         const int64_t *__restrict__ step, int64_t depth)
 {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < M) out[j] = in[perm[j]];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < M) sig[pmod(step[0], depth) * M + j] = in[perm[j]];
 }
 
 // ---------------------------------------------------------------------------
@@ -51,12 +60,15 @@ __global__ void k_ingest(const double *__restrict__ in, const int32_t *__restric
 // the tile with plain coalesced stores, so no global atomics are needed.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void k_spread(const double *__restrict__ sig_cur, const double *__restrict__ sig_lag,
+__global__ __launch_bounds__(256) void k_spread(const double *__restrict__ sig, const int64_t *__restrict__ step,
                                                 const int2 *__restrict__ base, const R *__restrict__ wts,
                                                 const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_src,
-                                                typename cplx<R>::T *__restrict__ grid, int w, int ntx, int Lpad)
+                                                typename cplx<R>::T *__restrict__ grid, int w, int ntx, int Lpad, Geom g)
 {
     using C = typename cplx<R>::T;
+    const int64_t m = step[0] - g.lookahead;
+    const double *__restrict__ sig_cur = sig + pmod(m, g.sig_depth) * g.M;
+    const double *__restrict__ sig_lag = sig + pmod(m - g.LA, g.sig_depth) * g.M;
     __shared__ R acc_re[kTile * kTile];
     __shared__ R acc_im[kTile * kTile];
     const int tile = blockIdx.x, tx = tile % ntx, ty = tile / ntx;
@@ -275,33 +287,72 @@ __device__ __forceinline__ int ilog2(int q)
 // ---------------------------------------------------------------------------
 template <class R, int MODE>
 __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__restrict__ in, typename cplx<R>::T *__restrict__ out,
-                         const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
+                                                const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
 {
     using C = typename cplx<R>::T;
     extern __shared__ char smem[];
     C *lds = reinterpret_cast<C *>(smem);
     const int line = blockIdx.x, tid = threadIdx.x, T = g.Q >> 4, L = ilog2(g.Q);
     const C *x = in + (size_t)line * g.Lpad;
-    C v[16];
     const int nx = line - g.R;
-    for (int s = 0; s < g.P; ++s) {
-        // the line is re-read for each branch (from L2) rather than held in registers
+    C v[16];
+    if constexpr (sizeof(R) == 4) {
+        // Decimation in time over the P branches: x_s[m'] = x[P m' + s],
+        // X(k) = sum_s e^{2 pi i k s/nf} FFT_Q(x_s)[k mod Q].  Slot k'' = k mod Q serves
+        // n = k'' (if k'' <= R) and n = k'' - Q (if k'' >= Q - R); each thread accumulates
+        // its slots over the branches and writes every output once, in natural order.
+        C acc_p[16], acc_n[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int m = tid + r * T;
-            const C xm = m < g.Lpad ? x[m] : C{0, 0};
-            v[r] = s == 0 ? xm : cmul(xm, tw[(s * m) % g.nf]);
+        for (int i = 0; i < 16; ++i) acc_p[i] = acc_n[i] = C{0, 0};
+        for (int s = 0; s < g.P; ++s) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = g.P * (tid + r * T) + s;
+                v[r] = m < g.Lpad ? x[m] : C{0, 0};
+            }
+            fft_line(lds, v, g.Q, L, +1, tw, g.P);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int kk = tid + i * T;
+                const C y = lds[lpad(kk)];
+                if (kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, tw[(kk * s) % g.nf]));
+                if (kk >= g.Q - g.R) {
+                    const int n2 = kk - g.Q;
+                    acc_n[i] = cadd(acc_n[i], s == 0 ? y : cmul(y, tw[((n2 * s) % g.nf + g.nf) % g.nf]));
+                }
+            }
+            __syncthreads();
         }
-        fft_line(lds, v, g.Q, L, +1, tw, g.P);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int kp = tid + i * T;
-            int n;
-            if (!out_mode(kp, s, g, n)) continue;
-            if (MODE == 1 && (double)(nx * nx + n * n) > g.Rd2) continue;
-            out[(size_t)line * g.N + n + g.R] = cmul(lds[lpad(kp)], corr[n + g.R]);
+            const int kk = tid + i * T;
+            if (kk <= g.R && !(MODE == 1 && (double)(nx * nx + kk * kk) > g.Rd2))
+                out[(size_t)line * g.N + kk + g.R] = cmul(acc_p[i], corr[kk + g.R]);
+            const int n2 = kk - g.Q;
+            if (kk >= g.Q - g.R && !(MODE == 1 && (double)(nx * nx + n2 * n2) > g.Rd2))
+                out[(size_t)line * g.N + n2 + g.R] = cmul(acc_n[i], corr[n2 + g.R]);
         }
-        __syncthreads();
+    } else {
+        // FP64: decimation in frequency (fewer registers), k = P k' + s per branch
+        for (int s = 0; s < g.P; ++s) {
+            // the line is re-read for each branch (from L2) rather than held in registers
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = tid + r * T;
+                const C xm = m < g.Lpad ? x[m] : C{0, 0};
+                v[r] = s == 0 ? xm : cmul(xm, tw[(s * m) % g.nf]);
+            }
+            fft_line(lds, v, g.Q, L, +1, tw, g.P);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int kp = tid + i * T;
+                int n;
+                if (!out_mode(kp, s, g, n)) continue;
+                if (MODE == 1 && (double)(nx * nx + n * n) > g.Rd2) continue;
+                out[(size_t)line * g.N + n + g.R] = cmul(lds[lpad(kp)], corr[n + g.R]);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -398,9 +449,13 @@ __global__ __launch_bounds__(256) void k_transpose(const C *__restrict__ in, C *
 // Hermitian split of the packed transform: F = S(t_m) + i S(t_{m-LA}).
 template <class R>
 __global__ __launch_bounds__(256) void k_split(const typename cplx<R>::T *__restrict__ F, const ModeChunk *__restrict__ chunks,
-                                               typename cplx<R>::T *__restrict__ cur, typename cplx<R>::T *__restrict__ lag, Geom g)
+                                               typename cplx<R>::T *__restrict__ ring_cur, typename cplx<R>::T *__restrict__ ring_lag,
+                                               int64_t H, const int64_t *__restrict__ step, Geom g)
 {
     using C = typename cplx<R>::T;
+    const int64_t m = step[0] - g.lookahead;
+    C *__restrict__ cur = ring_cur + pmod(m, g.W) * H;
+    C *__restrict__ lag = ring_lag + pmod(m - g.LA, g.W) * H;
     const ModeChunk c = chunks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= c.cnt) return;
@@ -428,9 +483,10 @@ template <class R>
 __global__ __launch_bounds__(256) void k_near(const ModeChunk *__restrict__ chunks, const typename cplx<R>::T *__restrict__ cur,
                                               const typename cplx<R>::T *__restrict__ lag, double2 *__restrict__ Dst,
                                               double2 *__restrict__ Cst, const double *__restrict__ phi_in,
-                                              typename cplx<R>::T *__restrict__ atot, int64_t H, int64_t m, Geom g)
+                                              typename cplx<R>::T *__restrict__ atot, int64_t H, const int64_t *__restrict__ step, Geom g)
 {
     using C = typename cplx<R>::T;
+    const int64_t m = step[0] - g.lookahead;
     const ModeChunk c = chunks[blockIdx.x];
     const int t = threadIdx.x;
     if (t >= c.cnt) return;
@@ -504,9 +560,11 @@ __global__ __launch_bounds__(256) void k_far(const int32_t *__restrict__ far_pk,
                                              const double *__restrict__ Htab, const double *__restrict__ chi,
                                              const double *__restrict__ dec, const double *__restrict__ inj,
                                              double2 *__restrict__ B, const typename cplx<R>::T *__restrict__ lag,
-                                             typename cplx<R>::T *__restrict__ atot, int64_t n_far, int64_t H, int64_t m, Geom g)
+                                             typename cplx<R>::T *__restrict__ atot, int64_t n_far, int64_t H,
+                                             const int64_t *__restrict__ step, Geom g)
 {
     using C = typename cplx<R>::T;
+    const int64_t m = step[0] - g.lookahead;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t f = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (f >= n_far) return;
@@ -676,8 +734,9 @@ __device__ __forceinline__ int64_t sig_slot(int64_t m, int d, const Geom &g)
     return ((lvl % g.sig_depth) + g.sig_depth) % g.sig_depth;
 }
 
-__global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, int64_t m, Geom g)
+__global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, const int64_t *__restrict__ step, Geom g)
 {
+    const int64_t m = step[0] - g.lookahead;
     __shared__ double psi[kLocalPsi];          // [sc][n_reg][D]
     __shared__ double sigs[kLocalSig];         // [sc][nlev]
     __shared__ double2 spos[kLocalMaxSrc];
@@ -833,8 +892,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, int64_t m,
 // x = 2 sqrt((k+1) dt - r) / u_a - 1, both computed arithmetically.
 // ---------------------------------------------------------------------------
 template <int NL>
-__global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, int64_t m, Geom g)
+__global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int64_t *__restrict__ step, Geom g)
 {
+    const int64_t m = step[0] - g.lookahead;
     __shared__ double psi[kFastSrc * kFastRow];   // [source][row]
     __shared__ double sigs[kFastSrc * NL];
     __shared__ double2 spos[kFastSrc];
@@ -976,11 +1036,11 @@ __global__ void k_zero_f64(double *__restrict__ p, int64_t n)
 
 // u (caller order) = u_h + u_l, or zeros before the first reported step
 __global__ void k_combine(const double *__restrict__ uh, const double *__restrict__ ul, const int32_t *__restrict__ rank,
-                          double *__restrict__ u, int64_t Nx, int zero)
+                          double *__restrict__ u, int64_t Nx, const int64_t *__restrict__ step, int lookahead)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nx) return;
-    if (zero) {
+    if (step[0] - lookahead < 1) {   // u(t <= 0) = 0 (zero initial data)
         u[i] = 0.0;
         return;
     }
@@ -993,23 +1053,29 @@ __global__ void k_combine(const double *__restrict__ uh, const double *__restric
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_ingest(Plan &p, const double *sigma_in, int64_t slot)
+hipError_t launch_step_begin(Plan &p)
 {
-    hipLaunchKernelGGL(k_ingest, dim3(nblk(p.M, 256)), dim3(256), 0, p.stream, sigma_in, p.d_src_perm, p.d_sig + slot * p.M, p.M);
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, p.stream, p.d_step);
     return hipGetLastError();
 }
 
-hipError_t launch_spread(Plan &p, int64_t slot_cur, int64_t slot_lag)
+hipError_t launch_ingest(Plan &p, const double *sigma_in)
+{
+    hipLaunchKernelGGL(k_ingest, dim3(nblk(p.M, 256)), dim3(256), 0, p.stream, sigma_in, p.d_src_perm, p.d_sig, p.M, p.d_step,
+                       p.g.sig_depth);
+    return hipGetLastError();
+}
+
+hipError_t launch_spread(Plan &p)
 {
     const Geom &g = p.g;
-    const double *sc = p.d_sig + slot_cur * p.M, *sl = p.d_sig + slot_lag * p.M;
     const unsigned nt = (unsigned)(g.ntx * g.ntx);
     if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_spread<float>, dim3(nt), dim3(256), 0, p.stream, sc, sl, p.d_src_base, (const float *)p.d_src_wts,
-                           p.d_tile_off, p.d_tile_src, (float2 *)p.d_grid, g.w, g.ntx, g.Lpad);
+        hipLaunchKernelGGL(k_spread<float>, dim3(nt), dim3(256), 0, p.stream, p.d_sig, p.d_step, p.d_src_base,
+                           (const float *)p.d_src_wts, p.d_tile_off, p.d_tile_src, (float2 *)p.d_grid, g.w, g.ntx, g.Lpad, g);
     else
-        hipLaunchKernelGGL(k_spread<double>, dim3(nt), dim3(256), 0, p.stream, sc, sl, p.d_src_base, (const double *)p.d_src_wts,
-                           p.d_tile_off, p.d_tile_src, (double2 *)p.d_grid, g.w, g.ntx, g.Lpad);
+        hipLaunchKernelGGL(k_spread<double>, dim3(nt), dim3(256), 0, p.stream, p.d_sig, p.d_step, p.d_src_base,
+                           (const double *)p.d_src_wts, p.d_tile_off, p.d_tile_src, (double2 *)p.d_grid, g.w, g.ntx, g.Lpad, g);
     return hipGetLastError();
 }
 
@@ -1069,42 +1135,42 @@ hipError_t launch_fft_cols1(Plan &p)
     return hipGetLastError();
 }
 
-hipError_t launch_split(Plan &p, int64_t ring_cur, int64_t ring_lag)
+hipError_t launch_split(Plan &p)
 {
     const Geom &g = p.g;
     const int64_t H = p.n_modes;
     if (p.precision == WFP2D_PREC_MIXED)
         hipLaunchKernelGGL(k_split<float>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, (const float2 *)p.d_F, p.d_chunks,
-                           (float2 *)p.d_ring_cur + ring_cur * H, (float2 *)p.d_ring_lag + ring_lag * H, g);
+                           (float2 *)p.d_ring_cur, (float2 *)p.d_ring_lag, H, p.d_step, g);
     else
         hipLaunchKernelGGL(k_split<double>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, (const double2 *)p.d_F, p.d_chunks,
-                           (double2 *)p.d_ring_cur + ring_cur * H, (double2 *)p.d_ring_lag + ring_lag * H, g);
+                           (double2 *)p.d_ring_cur, (double2 *)p.d_ring_lag, H, p.d_step, g);
     return hipGetLastError();
 }
 
-hipError_t launch_near(Plan &p, int64_t m)
+hipError_t launch_near(Plan &p)
 {
     const Geom &g = p.g;
     if (p.precision == WFP2D_PREC_MIXED)
         hipLaunchKernelGGL(k_near<float>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, p.d_chunks, (const float2 *)p.d_ring_cur,
-                           (const float2 *)p.d_ring_lag, p.d_D, p.d_C, p.d_phi_in, (float2 *)p.d_atot, p.n_modes, m, g);
+                           (const float2 *)p.d_ring_lag, p.d_D, p.d_C, p.d_phi_in, (float2 *)p.d_atot, p.n_modes, p.d_step, g);
     else
         hipLaunchKernelGGL(k_near<double>, dim3((unsigned)p.n_chunks), dim3(kChunk), 0, p.stream, p.d_chunks, (const double2 *)p.d_ring_cur,
-                           (const double2 *)p.d_ring_lag, p.d_D, p.d_C, p.d_phi_in, (double2 *)p.d_atot, p.n_modes, m, g);
+                           (const double2 *)p.d_ring_lag, p.d_D, p.d_C, p.d_phi_in, (double2 *)p.d_atot, p.n_modes, p.d_step, g);
     return hipGetLastError();
 }
 
-hipError_t launch_far(Plan &p, int64_t m)
+hipError_t launch_far(Plan &p)
 {
     const Geom &g = p.g;
     if (p.n_far == 0) return hipSuccess;
     const unsigned nb = nblk(p.n_far, 4);
     if (p.precision == WFP2D_PREC_MIXED)
         hipLaunchKernelGGL(k_far<float>, dim3(nb), dim3(256), 0, p.stream, p.d_far_pk, p.d_far_cls, p.d_H, p.d_chi, p.d_dec, p.d_inj,
-                           p.d_B, (const float2 *)p.d_ring_lag, (float2 *)p.d_atot, p.n_far, p.n_modes, m, g);
+                           p.d_B, (const float2 *)p.d_ring_lag, (float2 *)p.d_atot, p.n_far, p.n_modes, p.d_step, g);
     else
         hipLaunchKernelGGL(k_far<double>, dim3(nb), dim3(256), 0, p.stream, p.d_far_pk, p.d_far_cls, p.d_H, p.d_chi, p.d_dec, p.d_inj,
-                           p.d_B, (const double2 *)p.d_ring_lag, (double2 *)p.d_atot, p.n_far, p.n_modes, m, g);
+                           p.d_B, (const double2 *)p.d_ring_lag, (double2 *)p.d_atot, p.n_far, p.n_modes, p.d_step, g);
     return hipGetLastError();
 }
 
@@ -1152,7 +1218,7 @@ hipError_t launch_interp(Plan &p)
     return hipGetLastError();
 }
 
-hipError_t launch_local(Plan &p, int64_t m)
+hipError_t launch_local(Plan &p)
 {
     LocalArgs A;
     A.txy = p.d_tgt_xy;
@@ -1181,12 +1247,12 @@ hipError_t launch_local(Plan &p, int64_t m)
         const int cells = p.ncell * p.ncell;
         const unsigned grid = (unsigned)std::min(cells, 2 * 256);
         if (p.g.nlev == 35)
-            hipLaunchKernelGGL(k_local_fast<35>, dim3(grid), dim3(threads), 0, p.stream, A, m, p.g);
+            hipLaunchKernelGGL(k_local_fast<35>, dim3(grid), dim3(threads), 0, p.stream, A, p.d_step, p.g);
         else
-            hipLaunchKernelGGL(k_local_fast<43>, dim3(grid), dim3(threads), 0, p.stream, A, m, p.g);
+            hipLaunchKernelGGL(k_local_fast<43>, dim3(grid), dim3(threads), 0, p.stream, A, p.d_step, p.g);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_local, dim3((unsigned)(p.ncell * p.ncell)), dim3(kLocalThreads), 0, p.stream, A, m, p.g);
+    hipLaunchKernelGGL(k_local, dim3((unsigned)(p.ncell * p.ncell)), dim3(kLocalThreads), 0, p.stream, A, p.d_step, p.g);
     return hipGetLastError();
 }
 
@@ -1196,9 +1262,10 @@ hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n)
     return hipGetLastError();
 }
 
-hipError_t launch_combine(Plan &p, double *u_out, int zero)
+hipError_t launch_combine(Plan &p, double *u_out)
 {
-    hipLaunchKernelGGL(k_combine, dim3(nblk(p.Nx, 256)), dim3(256), 0, p.stream, p.d_uh, p.d_ul, p.d_tgt_rank, u_out, p.Nx, zero);
+    hipLaunchKernelGGL(k_combine, dim3(nblk(p.Nx, 256)), dim3(256), 0, p.stream, p.d_uh, p.d_ul, p.d_tgt_rank, u_out, p.Nx, p.d_step,
+                       p.lookahead);
     return hipGetLastError();
 }
 

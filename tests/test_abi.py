@@ -34,3 +34,14 @@ def test_errors_are_status_codes_without_a_device():
     assert lib.wfp2d_destroy(None) == 0
     with pytest.raises(pa.Wfp2dError):
         pa.host_eval(99, [], 1)
+
+
+def test_graph_and_batch_entry_points_reject_without_a_device():
+    lib = pa.load_library()
+    assert lib.wfp2d_graph_capture(None, None, None) == -6
+    assert lib.wfp2d_graph_launch(None) == -6
+    b = ctypes.c_void_p()
+    assert lib.wfp2d_batch_create(ctypes.byref(b), 0, None, None, None, 1, None) == -1
+    assert b.value is None
+    assert lib.wfp2d_batch_launch(None) == -6
+    assert lib.wfp2d_batch_destroy(None) == 0

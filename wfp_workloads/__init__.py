@@ -235,6 +235,23 @@ def config(idx: int, displaced_targets: bool = False) -> Workload:
     return w
 
 
+def batch_instances(n: int = 64, nt: int = 1000, W: int = 16, tol: float = 1e-7,
+                    m_range=(500, 20000), l_range=(10.0, 50.0)) -> list:
+    """Independent scatterers of uneven size: star curves with M_i log-uniform in m_range
+    and L_i ~ U(l_range) wavelengths across B, family E signatures, the time step of
+    eq. dt with the Sec. 5.2 margin for each instance's bandwidth."""
+    rng = np.random.default_rng(1003)
+    L = rng.uniform(*l_range, size=n)
+    M = np.floor(np.exp(rng.uniform(math.log(m_range[0]), math.log(m_range[1]), size=n))).astype(np.int64)
+    out = []
+    for i in range(n):
+        r = np.random.default_rng(1003000 + i)
+        src = star_curve(int(M[i]))
+        out.append(family_e_workload(f"cfg3_inst{i}_M{int(M[i])}_{L[i]:.1f}wl_E", r, src, L=float(L[i]), nt=nt,
+                                     W=W, tol=tol))
+    return out
+
+
 def tiny(seed: int = 7, M: int = 16, L: float = 2.0, nt: int = 60, family: str = "G",
          displaced_targets: bool = True) -> Workload:
     """A few-source case small enough for exhaustive oracle checks."""
