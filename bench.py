@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--cpu-sample-targets", type=int, default=1,
                     help="targets of the CPU oracle sample (at the last timed step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default spreading tile shape")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a device-to-device copy of this many GiB (calibrates HBM byte counters)")
@@ -115,6 +116,11 @@ def main():
         f"band={info['band']} pairs={info['n_local_pairs']} lookahead={L} HBM={info['bytes_device'] / 2**30:.1f}GiB")
     params = w.torch_params(dev)
     u = torch.empty(w.Nx, dtype=torch.float64, device=dev)
+    tuning = None
+    if not args.no_autotune:
+        from paper_2604_07170_amd.autotune import tune_spread
+        tuning = tune_spread(plan)
+        log(f"[bench] spreading tile {tuning['tile']} ({tuning['class']}): {tuning['ms']}")
 
     # ---- warm-up: the full pipeline, so the timed window starts at step warmup+1 ----
     t0 = time.time()
@@ -220,7 +226,8 @@ def main():
         "config": {"workload": w.name, "M": w.M, "Nx": w.Nx, "dt": w.dt, "W": w.W, "p": w.p, "eps": w.tol,
                    "timed_steps": f"{args.warmup + 1}..{args.warmup + K} (reported u at t_{step_reported - K + 1}.."
                                   f"t_{step_reported})", "precision": args.precision,
-                   "n_modes": info["n_modes"], "nf": info["nf"], "local_pairs": info["n_local_pairs"]},
+                   "n_modes": info["n_modes"], "nf": info["nf"], "local_pairs": info["n_local_pairs"],
+                   "spread_tile": list(pa.Wfp2d.SPREAD_TILES[plan.info()["spread_tile"]])},
         "roofline": roof,
         "hbm_roofline_step_frac": round(step_hbm_frac, 4),
         "stages": per_stage,

@@ -66,11 +66,12 @@ typedef struct {
     double a;         /* near/far split margin, A+ = A + a (eq. Ap); 0 = rule max(1, delta + ln(1e15)/lambda_max) */
     double Kf;        /* far-history Fourier cutoff (eq. ufhApprox); default 80 (Sec. 5) */
     double b_Delta;   /* shape parameter of the radial blend; default 30 (reproduces Table 1) */
-    double nufft_tol; /* 0 = default (1e-7 mixed, 1e-11 FP64) */
+    double nufft_tol; /* 0 = default (1e-7 mixed, 1e-11 FP64), else in [1e-15, 1e-2) */
     int64_t max_steps;/* steps the plan will be run for; 0 = unchecked.  Used to check the
                          sum-of-exponentials validity range T <~ 3e4 (Sec. 2.3). */
     int32_t device;   /* HIP device ordinal */
     void *stream;     /* hipStream_t for every launch (NULL = default stream) */
+    int32_t spread_tile; /* type-1 spreading tile shape, 0 = default (3); see wfp2d_set_spread_tile */
 } wfp2d_opts;
 
 typedef struct {
@@ -96,6 +97,7 @@ typedef struct {
     int64_t step_reported; /* n such that wfp2d_evaluate returns u(t_n) (<= 0: zero field) */
     int32_t precision;
     int32_t n_regular_subpanels; /* local-weight sub-panels with r >= dt/2 */
+    int32_t spread_tile;         /* current spreading tile shape code */
 } wfp2d_info;
 
 /* Fill *opts with the defaults listed above.  Never fails for a valid pointer. */
@@ -183,8 +185,8 @@ wfp2d_status wfp2d_graph_launch(wfp2d_plan plan);
  * plan i (as for wfp2d_graph_capture); stream is the (non-default) hipStream_t
  * the batch is launched on.  The plans' work is captured on n_streams
  * forked capture streams (>= 1), so different plans may run concurrently.
- * The plans must outlive the batch and must not be stepped otherwise while
- * it is in use.  Errors (message via wfp2d_last_error(NULL)): ERR_ARG, ERR_STATE,
+ * The plans must outlive the batch (destroy the batch first) and must not be
+ * stepped otherwise while it is in use.  Errors (message via wfp2d_last_error(NULL)): ERR_ARG, ERR_STATE,
  * ERR_DEVICE, ERR_NOMEM.
  */
 typedef struct wfp2d_batch_s *wfp2d_batch;
@@ -192,6 +194,22 @@ wfp2d_status wfp2d_batch_create(wfp2d_batch *out, int32_t n, const wfp2d_plan *p
                                 double *const *u, int32_t n_streams, void *stream);
 wfp2d_status wfp2d_batch_launch(wfp2d_batch batch);
 wfp2d_status wfp2d_batch_destroy(wfp2d_batch batch);
+
+/*
+ * Spreading tile shape of the type-1 NUFFT (eq. sighat: the sources' kernel
+ * contributions are summed per tile of the fine grid in on-chip memory).
+ * code 1..5 = 8x8, 16x8, 16x16, 32x16, 32x32 fine-grid points.  The result
+ * does not depend on the shape (up to the order of floating-point sums); the
+ * speed does, with the source density, so an autotuner picks it by timing.
+ * wfp2d_set_spread_tile rebuilds the plan's per-tile source lists (it
+ * synchronises the plan's stream); wfp2d_time_spread selects `code` the same
+ * way and returns the mean duration in ms of `reps` spreading launches on the
+ * plan's stream (it only rewrites the plan's scratch grid, so it may be called
+ * between steps).  Both fail with ERR_STATE while a graph of the plan, or a
+ * batch holding it, exists; ERR_ARG for a bad code.
+ */
+wfp2d_status wfp2d_set_spread_tile(wfp2d_plan plan, int32_t code);
+wfp2d_status wfp2d_time_spread(wfp2d_plan plan, int32_t code, int32_t reps, double *ms);
 
 /*
  * Per-stage timing with HIP events recorded on the plan's stream around every

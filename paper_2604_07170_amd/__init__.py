@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("interp_order", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("Delta", ctypes.c_double), ("a", ctypes.c_double), ("Kf", ctypes.c_double),
                 ("b_Delta", ctypes.c_double), ("nufft_tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
-                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("spread_tile", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -50,7 +50,8 @@ class Info(ctypes.Structure):
                    ("n_subpanels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32)]
                 + [(n, ctypes.c_int64) for n in ("M", "Nx", "n_local_pairs", "sigma_depth", "bytes_device",
                                                  "steps_ingested", "step_reported")]
-                + [("precision", ctypes.c_int32), ("n_regular_subpanels", ctypes.c_int32)])
+                + [("precision", ctypes.c_int32), ("n_regular_subpanels", ctypes.c_int32),
+                   ("spread_tile", ctypes.c_int32)])
 
 
 _lib = None
@@ -84,9 +85,12 @@ def load_library():
                                        ctypes.POINTER(vp), i32, vp]
     lib.wfp2d_batch_launch.argtypes = [vp]
     lib.wfp2d_batch_destroy.argtypes = [vp]
+    lib.wfp2d_set_spread_tile.argtypes = [vp, i32]
+    lib.wfp2d_time_spread.argtypes = [vp, i32, i32, dp]
     for f in ("wfp2d_default_opts", "wfp2d_init", "wfp2d_step", "wfp2d_evaluate", "wfp2d_query", "wfp2d_destroy",
               "wfp2d_debug_copy", "wfp2d_host_eval", "wfp2d_set_timing", "wfp2d_get_timing", "wfp2d_graph_capture",
-              "wfp2d_graph_launch", "wfp2d_batch_create", "wfp2d_batch_launch", "wfp2d_batch_destroy"):
+              "wfp2d_graph_launch", "wfp2d_batch_create", "wfp2d_batch_launch", "wfp2d_batch_destroy",
+              "wfp2d_set_spread_tile", "wfp2d_time_spread"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -135,7 +139,8 @@ class Wfp2d:
 
     def __init__(self, src_xy, tgt_xy, dt: float, W: int, tol: float = 1e-7, *, precision: str = "mixed",
                  interp_order: int = 20, lookahead: int = -1, Delta: float = 1.0, a: float = 0.0, Kf: float = 80.0,
-                 b_Delta: float = 30.0, nufft_tol: float = 0.0, max_steps: int = 0, device: int = 0, stream=None):
+                 b_Delta: float = 30.0, nufft_tol: float = 0.0, max_steps: int = 0, device: int = 0, stream=None,
+                 spread_tile: int = 0):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -146,7 +151,7 @@ class Wfp2d:
         o.precision = PREC_MIXED if precision == "mixed" else PREC_FP64
         o.interp_order, o.lookahead = int(interp_order), int(lookahead)
         o.Delta, o.a, o.Kf, o.b_Delta, o.nufft_tol = float(Delta), float(a), float(Kf), float(b_Delta), float(nufft_tol)
-        o.max_steps, o.device = int(max_steps), int(device)
+        o.max_steps, o.device, o.spread_tile = int(max_steps), int(device), int(spread_tile)
         self.device = torch.device("cuda", int(device))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -188,6 +193,18 @@ class Wfp2d:
             raise ValueError("out must be a contiguous float64 CUDA tensor with Nx elements")
         self._check(self.lib.wfp2d_evaluate(self.h, ctypes.c_void_p(out.data_ptr())))
         return out
+
+    # -- spreading tile shape (autotuned by paper_2604_07170_amd.autotune) --
+    SPREAD_TILES = {1: (8, 8), 2: (16, 8), 3: (16, 16), 4: (32, 16), 5: (32, 32)}
+
+    def set_spread_tile(self, code: int):
+        self._check(self.lib.wfp2d_set_spread_tile(self.h, int(code)))
+
+    def time_spread(self, code: int, reps: int = 10) -> float:
+        """Mean ms of `reps` spreading launches with tile shape `code` (which stays selected)."""
+        ms = ctypes.c_double(0.0)
+        self._check(self.lib.wfp2d_time_spread(self.h, int(code), int(reps), ctypes.byref(ms)))
+        return ms.value
 
     # -- graph replay --
     def graph_capture(self, sigma, u):
@@ -254,11 +271,17 @@ class Batch:
 
     sigma[i] / u[i] are fixed float64 CUDA tensors of plan i (M_i / Nx_i elements);
     the caller fills sigma[i] with sigma_j(t_n) before each launch and reads u[i]
-    (u at t_{n - lookahead_i}) after it."""
+    (u at t_{n - lookahead_i}) after it.  autotune=True first picks each plan's
+    spreading tile shape by timing (cached per size class, see autotune)."""
 
-    def __init__(self, plans, sigma, u, n_streams: int = 4, stream=None):
+    def __init__(self, plans, sigma, u, n_streams: int = 4, stream=None, autotune: bool = False,
+                 tune_cache: str | None = None):
         import torch
         self.lib = load_library()
+        self.tuning = []
+        if autotune:
+            from .autotune import tune_spread
+            self.tuning = [tune_spread(p, cache=tune_cache) for p in plans]
         n = len(plans)
         if not (n == len(sigma) == len(u)) or n == 0:
             raise ValueError("plans, sigma and u must be non-empty lists of equal length")

@@ -46,6 +46,17 @@ T *Plan::alloc(int64_t count)
     return (T *)ptr;
 }
 
+void Plan::release(void *ptr)
+{
+    if (!ptr) return;
+    for (size_t i = 0; i < allocs.size(); ++i)
+        if (allocs[i] == ptr) {
+            (void)hipFree(ptr);
+            allocs.erase(allocs.begin() + (std::ptrdiff_t)i);
+            return;
+        }
+}
+
 Plan::~Plan()
 {
     if (stream) (void)hipStreamSynchronize(stream);
@@ -122,6 +133,52 @@ static void *upload_real(Plan &p, const std::vector<double> &v)
     double *d = p.alloc<double>((int64_t)v.size());
     upload(d, v);
     return d;
+}
+
+// Spreading tile shapes: code -> tile edge in x and y (fine-grid points).
+static bool spread_tile_shape(int code, int &tx, int &ty)
+{
+    static const int shapes[6][2] = {{0, 0}, {8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
+    if (code < 1 || code > 5) return false;
+    tx = shapes[code][0];
+    ty = shapes[code][1];
+    return true;
+}
+
+// Per-tile source lists of the spreading kernel for tile shape `code`: every
+// source is listed in each tile its w x w kernel support meets.
+static void build_spread_tiles(Plan &p, int code)
+{
+    int tx, ty;
+    if (!spread_tile_shape(code, tx, ty)) fail(WFP2D_ERR_ARG, "spread tile code must be in [1, 5]");
+    const Geom &g = p.g;
+    const int w = g.w;
+    const int ntx = (g.Lpad + tx - 1) / tx, nty = (g.Lpad + ty - 1) / ty;
+    const int64_t ntile = (int64_t)ntx * nty;
+    const std::vector<int2> &sb = p.h_src_base;
+    const int64_t M = (int64_t)sb.size();
+    std::vector<int32_t> off(ntile + 1, 0);
+    for (int64_t j = 0; j < M; ++j)
+        for (int y = sb[j].y / ty; y <= (sb[j].y + w - 1) / ty; ++y)
+            for (int x = sb[j].x / tx; x <= (sb[j].x + w - 1) / tx; ++x) off[(int64_t)y * ntx + x + 1]++;
+    for (int64_t t = 0; t < ntile; ++t) off[t + 1] += off[t];
+    std::vector<int32_t> pos(off.begin(), off.end() - 1), lst(off[ntile]);
+    for (int64_t j = 0; j < M; ++j)
+        for (int y = sb[j].y / ty; y <= (sb[j].y + w - 1) / ty; ++y)
+            for (int x = sb[j].x / tx; x <= (sb[j].x + w - 1) / tx; ++x) lst[pos[(int64_t)y * ntx + x]++] = (int32_t)j;
+    p.release(p.d_tile_off);
+    p.release(p.d_tile_src);
+    p.d_tile_off = nullptr;
+    p.d_tile_src = nullptr;
+    p.d_tile_off = p.alloc<int32_t>(ntile + 1);
+    upload(p.d_tile_off, off);
+    p.d_tile_src = p.alloc<int32_t>(off[ntile]);
+    upload(p.d_tile_src, lst);
+    p.spread_tile = code;
+    p.sp_tx = tx;
+    p.sp_ty = ty;
+    p.sp_ntx = ntx;
+    p.sp_nty = nty;
 }
 
 static void build(Plan &p, const double *src_xy, const double *tgt_xy)
@@ -283,34 +340,8 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     kernel_data(sxy, sbase, swts);
     kernel_data(txy, tbase, twts);
     const int ntile = g.ntx * g.ntx;
-    {
-        // spreading: every source is listed in each tile its kernel support meets
-        auto tiles_of = [&](int64_t j, int &tx0, int &tx1, int &ty0, int &ty1) {
-            tx0 = sbase[j].x / kTile;
-            tx1 = (sbase[j].x + w - 1) / kTile;
-            ty0 = sbase[j].y / kTile;
-            ty1 = (sbase[j].y + w - 1) / kTile;
-        };
-        std::vector<int32_t> off(ntile + 1, 0);
-        for (int64_t j = 0; j < M; ++j) {
-            int tx0, tx1, ty0, ty1;
-            tiles_of(j, tx0, tx1, ty0, ty1);
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) off[ty * g.ntx + tx + 1]++;
-        }
-        for (int t = 0; t < ntile; ++t) off[t + 1] += off[t];
-        std::vector<int32_t> pos(off.begin(), off.end() - 1), lst(off[ntile]);
-        for (int64_t j = 0; j < M; ++j) {
-            int tx0, tx1, ty0, ty1;
-            tiles_of(j, tx0, tx1, ty0, ty1);
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) lst[pos[ty * g.ntx + tx]++] = (int32_t)j;
-        }
-        p.d_tile_off = p.alloc<int32_t>(ntile + 1);
-        upload(p.d_tile_off, off);
-        p.d_tile_src = p.alloc<int32_t>(off[ntile]);
-        upload(p.d_tile_src, lst);
-    }
+    p.h_src_base = sbase;
+    build_spread_tiles(p, p.spread_tile);
     // interpolation: each target belongs to the tile holding its kernel origin
     {
         std::vector<int32_t> off(ntile + 1, 0), lst(Nx);
@@ -485,6 +516,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     p.d_panel_l2n = p.alloc<int32_t>(p.W);
     upload(p.d_panel_l2n, LT.panel_l2n);
     hip_check(fft_setup(p), "FFT kernel attributes");
+    hip_check(spread_setup(p), "spreading kernel attributes");
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize after set-up");
 }
 
@@ -611,6 +643,7 @@ wfp2d_status wfp2d_default_opts(wfp2d_opts *o)
     o->max_steps = 0;
     o->device = 0;
     o->stream = nullptr;
+    o->spread_tile = 0;
     return WFP2D_OK;
 }
 
@@ -630,6 +663,9 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
         if (opts) o = *opts;
         if (o.precision != WFP2D_PREC_FP64 && o.precision != WFP2D_PREC_MIXED) fail(WFP2D_ERR_ARG, "unknown precision");
         if (o.interp_order < 2 || o.interp_order > 32) fail(WFP2D_ERR_ARG, "interp_order must be in [2, 32]");
+        if (o.spread_tile < 0 || o.spread_tile > 5) fail(WFP2D_ERR_ARG, "spread_tile must be in [0, 5]");
+        if (!(o.nufft_tol == 0.0 || (o.nufft_tol >= 1e-15 && o.nufft_tol < 1e-2)))
+            fail(WFP2D_ERR_ARG, "nufft_tol must be 0 or in [1e-15, 1e-2) (kernel widths up to 16)");
         if (!(o.Delta > 0.0) || !(o.Kf > 0.0) || !(o.b_Delta > 0.0) || o.a < 0.0) fail(WFP2D_ERR_ARG, "bad Delta, Kf, b_Delta or a");
         for (int64_t i = 0; i < M; ++i)
             if (!(std::fabs(src_xy[2 * i]) <= 1.0 && std::fabs(src_xy[2 * i + 1]) <= 1.0))
@@ -658,6 +694,7 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
         p.nufft_tol = o.nufft_tol;
         p.device = o.device;
         p.stream = (hipStream_t)o.stream;
+        p.spread_tile = o.spread_tile ? o.spread_tile : 3;
         build(p, src_xy, tgt_xy);
         *out = h;
         return WFP2D_OK;
@@ -737,6 +774,7 @@ wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
     info->steps_ingested = p.steps;
     info->step_reported = p.steps - p.lookahead;
     info->precision = p.precision;
+    info->spread_tile = p.spread_tile;
     info->n_regular_subpanels = p.n_reg;
     return WFP2D_OK;
 }
@@ -888,6 +926,7 @@ wfp2d_status wfp2d_batch_create(wfp2d_batch *out, int32_t n, const wfp2d_plan *p
             throw;
         }
         for (int i = 0; i < n; ++i) plans[i]->p.stream = saved[i];
+        for (int i = 0; i < n; ++i) plans[i]->p.batch_refs += 1;
         *out = b;
         return WFP2D_OK;
     } catch (const Failure &f) {
@@ -918,7 +957,48 @@ wfp2d_status wfp2d_batch_destroy(wfp2d_batch b)
 {
     if (!b) return WFP2D_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (wfp2d_plan pl : b->plans) pl->p.batch_refs -= 1;
     delete b;
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_set_spread_tile(wfp2d_plan plan, int32_t code)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        if (p.graph_exec || p.batch_refs) fail(WFP2D_ERR_STATE, "a captured graph uses the current tile lists");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+        build_spread_tiles(p, code);
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_time_spread(wfp2d_plan plan, int32_t code, int32_t reps, double *ms)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        if (!ms || reps < 1) fail(WFP2D_ERR_ARG, "bad reps or NULL ms");
+        if (p.graph_exec || p.batch_refs) fail(WFP2D_ERR_STATE, "a captured graph uses the current tile lists");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+        if (code != p.spread_tile) build_spread_tiles(p, code);
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+        hip_check(launch_spread(p), "spread");   // warm-up
+        hip_check(hipEventRecord(e0, p.stream), "hipEventRecord");
+        for (int r = 0; r < reps; ++r) hip_check(launch_spread(p), "spread");
+        hip_check(hipEventRecord(e1, p.stream), "hipEventRecord");
+        hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float t = 0.f;
+        hip_check(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms = (double)t / reps;
+    });
     return WFP2D_OK;
 }
 

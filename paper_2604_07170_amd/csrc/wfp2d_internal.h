@@ -59,6 +59,7 @@ struct Plan;
 hipError_t launch_step_begin(Plan &p);
 hipError_t launch_ingest(Plan &p, const double *sigma_in);
 hipError_t launch_spread(Plan &p);
+hipError_t spread_setup(Plan &p);
 hipError_t fft_setup(Plan &p);
 hipError_t launch_fft_rows1(Plan &p);
 hipError_t launch_fft_cols1(Plan &p);
@@ -114,6 +115,9 @@ struct Plan {
     int2 *d_src_base = nullptr;       // band-local kernel origin per sorted source
     void *d_src_wts = nullptr;        // [M][2w] Real
     int32_t *d_tile_off = nullptr, *d_tile_src = nullptr;
+    std::vector<int2> h_src_base;     // host copy, to rebuild the tile lists for another tile shape
+    int32_t spread_tile = 3;          // tile shape code (see wfp2d_set_spread_tile)
+    int32_t sp_tx = 32, sp_ty = 32, sp_ntx = 1, sp_nty = 1;
     void *d_grid = nullptr;           // [Lpad][Lpad] complex Real
     void *d_T1 = nullptr;             // [Lpad][N] complex Real (rows transformed)
     void *d_T1t = nullptr;            // [N][Lpad] its transpose
@@ -162,6 +166,7 @@ struct Plan {
     // graph replay of one step + evaluation
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    int32_t batch_refs = 0;           // batches whose graphs hold this plan's buffers
 
     // stage timing (events recorded around launches when enabled)
     static constexpr int kStages = 12;
@@ -173,6 +178,7 @@ struct Plan {
 
     template <class T>
     T *alloc(int64_t count);
+    void release(void *ptr);          // free one allocation made by alloc
     ~Plan();
 };
 

@@ -55,52 +55,86 @@ __global__ void k_ingest(const double *__restrict__ in, const int32_t *__restric
 
 // ---------------------------------------------------------------------------
 // Type-1 spreading of c_j = sigma_cur[j] + i sigma_lag[j] onto the band grid.
-// One workgroup owns one kTile x kTile tile: it accumulates, in LDS, every
-// source whose kernel support meets the tile (a precomputed list) and writes
-// the tile with plain coalesced stores, so no global atomics are needed.
+// One wave owns one TX x TY tile of the grid and a precomputed list of the
+// sources whose w x w kernel support meets the tile.  Each lane owns PPL =
+// TX*TY/64 fixed grid points (column x = lane mod TX, rows y0 + i*(64/TX)) and
+// keeps their sums in registers: the list is staged in LDS 64 sources at a
+// time (one source per lane: sample pair, kernel origin, 2w weights), then
+// every lane adds each staged source's contribution to its own points.  No
+// two lanes write the same point, so there are no atomics and no LDS traffic
+// on the accumulators; the tile is written once with coalesced stores.
+// Consecutive workgroups go to different XCDs, so the tile order is remapped
+// to give each XCD a contiguous band of tiles (neighbouring tiles share
+// sources, which then stay in that XCD's L2).
 // ---------------------------------------------------------------------------
-template <class R>
-__global__ __launch_bounds__(256) void k_spread(const double *__restrict__ sig, const int64_t *__restrict__ step,
-                                                const int2 *__restrict__ base, const R *__restrict__ wts,
-                                                const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_src,
-                                                typename cplx<R>::T *__restrict__ grid, int w, int ntx, int Lpad, Geom g)
+template <class R, int TX, int TY>
+__global__ __launch_bounds__(64) void k_spread(const double *__restrict__ sig, const int64_t *__restrict__ step,
+                                               const int2 *__restrict__ base, const R *__restrict__ wts,
+                                               const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_src,
+                                               typename cplx<R>::T *__restrict__ grid, int w, int ntx, int ntile,
+                                               int Lpad, Geom g)
 {
     using C = typename cplx<R>::T;
+    constexpr int S = 64 / TX, PPL = TX * TY / 64;
+    static_assert(TX * TY % 64 == 0 && 64 % TX == 0, "tile shape");
+    extern __shared__ unsigned char spread_lds[];
+    __shared__ R st_c[64][2];
+    __shared__ int2 st_b[64];
+    const int ws = 2 * w + 1;                      // staged weights per source (odd stride: no bank aliasing)
+    R *st_w = (R *)spread_lds;                     // [64][ws]
+    const int per_xcd = (ntile + 7) >> 3;
+    const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= ntile) return;
     const int64_t m = step[0] - g.lookahead;
     const double *__restrict__ sig_cur = sig + pmod(m, g.sig_depth) * g.M;
     const double *__restrict__ sig_lag = sig + pmod(m - g.LA, g.sig_depth) * g.M;
-    __shared__ R acc_re[kTile * kTile];
-    __shared__ R acc_im[kTile * kTile];
-    const int tile = blockIdx.x, tx = tile % ntx, ty = tile / ntx;
-    const int ox = tx * kTile, oy = ty * kTile;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < kTile * kTile; i += blockDim.x) {
-        acc_re[i] = R(0);
-        acc_im[i] = R(0);
-    }
-    __syncthreads();
+    const int ox = (tile % ntx) * TX, oy = (tile / ntx) * TY;
+    const int lane = threadIdx.x;
+    const int px = lane % TX, py0 = lane / TX;     // this lane's points: (px, py0 + i S), i < PPL
+    R are[PPL], aim[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) are[i] = aim[i] = R(0);
     const int beg = tile_off[tile], end = tile_off[tile + 1];
-    const int wave = tid >> 6, lane = tid & 63, nwave = blockDim.x >> 6;
-    const int w2 = w * w;
-    for (int e = beg + wave; e < end; e += nwave) {
-        const int j = tile_src[e];
-        const R cr = (R)sig_cur[j], ci = (R)sig_lag[j];
-        const int2 b = base[j];
-        const R *wj = wts + (size_t)j * 2 * w;
-        for (int q = lane; q < w2; q += 64) {
-            const int a = q % w, bb = q / w;
-            const int gx = b.x + a - ox, gy = b.y + bb - oy;
-            if (gx >= 0 && gx < kTile && gy >= 0 && gy < kTile) {
-                const R k = wj[a] * wj[w + bb];
-                atomicAdd(&acc_re[gy * kTile + gx], cr * k);
-                atomicAdd(&acc_im[gy * kTile + gx], ci * k);
+    for (int r0 = beg; r0 < end; r0 += 64) {
+        const int e = r0 + lane;
+        if (e < end) {
+            const int j = tile_src[e];
+            st_c[lane][0] = (R)sig_cur[j];
+            st_c[lane][1] = (R)sig_lag[j];
+            const int2 b = base[j];
+            st_b[lane] = make_int2(b.x - ox, b.y - oy);
+            const R *wj = wts + (size_t)j * 2 * w;
+            for (int a = 0; a < 2 * w; ++a) st_w[lane * ws + a] = wj[a];
+        }
+        __syncthreads();
+        const int ns = min(64, end - r0);
+        for (int k = 0; k < ns; ++k) {
+            const int2 b = st_b[k];
+            const int dx = px - b.x;
+            if ((unsigned)dx < (unsigned)w) {
+                const R *wk = st_w + k * ws;
+                const R wx = wk[dx];
+                const R cr = st_c[k][0] * wx, ci = st_c[k][1] * wx;
+#pragma unroll
+                for (int i = 0; i < PPL; ++i) {
+                    const int dy = py0 + i * S - b.y;
+                    if ((unsigned)dy < (unsigned)w) {
+                        const R wy = wk[w + dy];
+                        are[i] += cr * wy;
+                        aim[i] += ci * wy;
+                    }
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = tid; i < kTile * kTile; i += blockDim.x) {
-        const int gy = i / kTile, gx = i % kTile;
-        grid[(size_t)(oy + gy) * Lpad + ox + gx] = C{acc_re[i], acc_im[i]};
+    const int gx = ox + px;
+    if (gx < Lpad) {
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) {
+            const int gy = oy + py0 + i * S;
+            if (gy < Lpad) grid[(size_t)gy * Lpad + gx] = C{are[i], aim[i]};
+        }
     }
 }
 
@@ -603,40 +637,39 @@ __global__ __launch_bounds__(256) void k_far(const int32_t *__restrict__ far_pk,
 
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
-// Type-2 interpolation: one workgroup per tile stages the tile's grid region
-// (kTile + w - 1)^2 in LDS; each target of the tile sums w^2 products.
+// Type-2 interpolation (eq. uhtraptrunc on the fine grid): u_h(x_i) = sum over
+// the w x w stencil of grid(origin_i + (a, b)) * wx_i[a] * wy_i[b].
+// Eight lanes serve one target: lane r sums the stencil rows r, r + 8 (a
+// contiguous run of w grid values each, read through the cache), and the
+// eight partial sums are reduced with lane shuffles.  Targets are taken in
+// tile order, so neighbouring targets read neighbouring grid lines.
+// Accumulation in FP64.
 // ---------------------------------------------------------------------------
-constexpr int kWmax = 16;
 template <class R>
 __global__ __launch_bounds__(256) void k_interp(const R *__restrict__ cgrid, const int2 *__restrict__ base, const R *__restrict__ wts,
-                                                const int32_t *__restrict__ toff, const int32_t *__restrict__ tlist,
-                                                double *__restrict__ uh, int w, int ntx, int Lpad)
+                                                const int32_t *__restrict__ tlist, double *__restrict__ uh, int w, int Lpad,
+                                                int64_t Nx)
 {
-    constexpr int RW = kTile + kWmax - 1;
-    __shared__ R reg[RW * RW];
-    const int tile = blockIdx.x, tx = tile % ntx, ty = tile / ntx;
-    const int ox = tx * kTile, oy = ty * kTile;
-    const int rw = kTile + w - 1;
-    for (int i = threadIdx.x; i < rw * rw; i += blockDim.x) {
-        const int yy = i / rw, xx = i % rw;
-        const int gy = oy + yy, gx = ox + xx;
-        reg[yy * RW + xx] = (gy < Lpad && gx < Lpad) ? cgrid[(size_t)gy * Lpad + gx] : R(0);
-    }
-    __syncthreads();
-    const int beg = toff[tile], end = toff[tile + 1];
-    for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
-        const int i = tlist[e];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = gid >> 3;
+    const int r = (int)(gid & 7);
+    double part = 0.0;
+    int i = 0;
+    if (e < Nx) {
+        i = tlist[e];
         const int2 b = base[i];
-        const R *wi = wts + (size_t)i * 2 * w;
-        const int bx = b.x - ox, by = b.y - oy;
-        double sum = 0.0;
-        for (int bb = 0; bb < w; ++bb) {
-            double row = 0.0;
-            for (int a = 0; a < w; ++a) row += (double)wi[a] * (double)reg[(by + bb) * RW + bx + a];
-            sum += row * (double)wi[w + bb];
+        const R *__restrict__ wi = wts + (size_t)i * 2 * w;
+        for (int bb = r; bb < w; bb += 8) {
+            const R *__restrict__ row = cgrid + (size_t)(b.y + bb) * Lpad + b.x;
+            double s = 0.0;
+            for (int a = 0; a < w; ++a) s += (double)wi[a] * (double)row[a];
+            part += s * (double)wi[w + bb];
         }
-        uh[i] = sum;
     }
+    part += __shfl_xor(part, 4, 8);
+    part += __shfl_xor(part, 2, 8);
+    part += __shfl_xor(part, 1, 8);
+    if (e < Nx && r == 0) uh[i] = part;
 }
 
 // ---------------------------------------------------------------------------
@@ -1066,18 +1099,38 @@ hipError_t launch_ingest(Plan &p, const double *sigma_in)
     return hipGetLastError();
 }
 
-hipError_t launch_spread(Plan &p)
+template <class R, int TX, int TY>
+static hipError_t spread_as(Plan &p)
 {
     const Geom &g = p.g;
-    const unsigned nt = (unsigned)(g.ntx * g.ntx);
-    if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_spread<float>, dim3(nt), dim3(256), 0, p.stream, p.d_sig, p.d_step, p.d_src_base,
-                           (const float *)p.d_src_wts, p.d_tile_off, p.d_tile_src, (float2 *)p.d_grid, g.w, g.ntx, g.Lpad, g);
-    else
-        hipLaunchKernelGGL(k_spread<double>, dim3(nt), dim3(256), 0, p.stream, p.d_sig, p.d_step, p.d_src_base,
-                           (const double *)p.d_src_wts, p.d_tile_off, p.d_tile_src, (double2 *)p.d_grid, g.w, g.ntx, g.Lpad, g);
+    const size_t lds = (size_t)64 * (2 * g.w + 1) * sizeof(R);
+    const int ntile = p.sp_ntx * p.sp_nty;
+    const unsigned nblk = (unsigned)(((ntile + 7) >> 3) << 3);
+    hipLaunchKernelGGL((k_spread<R, TX, TY>), dim3(nblk), dim3(64), lds, p.stream, p.d_sig, p.d_step, p.d_src_base,
+                       (const R *)p.d_src_wts, p.d_tile_off, p.d_tile_src, (typename cplx<R>::T *)p.d_grid, g.w,
+                       p.sp_ntx, ntile, g.Lpad, g);
     return hipGetLastError();
 }
+
+template <class R>
+static hipError_t spread_typed(Plan &p)
+{
+    switch (p.spread_tile) {
+    case 1: return spread_as<R, 8, 8>(p);
+    case 2: return spread_as<R, 16, 8>(p);
+    case 3: return spread_as<R, 16, 16>(p);
+    case 4: return spread_as<R, 32, 16>(p);
+    case 5: return spread_as<R, 32, 32>(p);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spread(Plan &p)
+{
+    return p.precision == WFP2D_PREC_MIXED ? spread_typed<float>(p) : spread_typed<double>(p);
+}
+
+hipError_t spread_setup(Plan &) { return hipSuccess; }
 
 static size_t fft_lds_bytes(const Plan &p) { return (size_t)(p.g.Q + p.g.Q / 16) * 2 * p.sizeof_real; }
 
@@ -1208,13 +1261,13 @@ hipError_t launch_fft_rows2(Plan &p)
 hipError_t launch_interp(Plan &p)
 {
     const Geom &g = p.g;
-    const unsigned nt = (unsigned)(g.ntx * g.ntx);
+    const unsigned nb = (unsigned)((p.Nx * 8 + 255) / 256);
     if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_interp<float>, dim3(nt), dim3(256), 0, p.stream, (const float *)p.d_cgrid, p.d_tgt_base,
-                           (const float *)p.d_tgt_wts, p.d_ttile_off, p.d_ttile_tgt, p.d_uh, g.w, g.ntx, g.Lpad);
+        hipLaunchKernelGGL(k_interp<float>, dim3(nb), dim3(256), 0, p.stream, (const float *)p.d_cgrid, p.d_tgt_base,
+                           (const float *)p.d_tgt_wts, p.d_ttile_tgt, p.d_uh, g.w, g.Lpad, p.Nx);
     else
-        hipLaunchKernelGGL(k_interp<double>, dim3(nt), dim3(256), 0, p.stream, (const double *)p.d_cgrid, p.d_tgt_base,
-                           (const double *)p.d_tgt_wts, p.d_ttile_off, p.d_ttile_tgt, p.d_uh, g.w, g.ntx, g.Lpad);
+        hipLaunchKernelGGL(k_interp<double>, dim3(nb), dim3(256), 0, p.stream, (const double *)p.d_cgrid, p.d_tgt_base,
+                           (const double *)p.d_tgt_wts, p.d_ttile_tgt, p.d_uh, g.w, g.Lpad, p.Nx);
     return hipGetLastError();
 }
 

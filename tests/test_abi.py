@@ -45,3 +45,20 @@ def test_graph_and_batch_entry_points_reject_without_a_device():
     assert b.value is None
     assert lib.wfp2d_batch_launch(None) == -6
     assert lib.wfp2d_batch_destroy(None) == 0
+
+
+def test_spread_tile_entry_points_reject_without_a_device():
+    lib = pa.load_library()
+    ms = ctypes.c_double(0.0)
+    assert lib.wfp2d_set_spread_tile(None, 3) == -6
+    assert lib.wfp2d_time_spread(None, 3, 1, ctypes.byref(ms)) == -6
+    o = pa.Opts()
+    lib.wfp2d_default_opts(ctypes.byref(o))
+    assert o.spread_tile == 0
+    o.spread_tile = 9
+    plan = ctypes.c_void_p()
+    xy = (ctypes.c_double * 2)(0.0, 0.0)
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.01, 24, 1e-7, ctypes.byref(o)) == -1
+    o.spread_tile = 0
+    o.nufft_tol = 1e-17
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.01, 24, 1e-7, ctypes.byref(o)) == -1

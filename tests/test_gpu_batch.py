@@ -63,7 +63,7 @@ def _instances():
     return [ws[i] for i in pick]
 
 
-def test_batch_uneven_instances_vs_alone_and_oracle():
+def test_batch_uneven_instances_vs_alone_and_oracle(tmp_path):
     import torch
     import paper_2604_07170_amd as pa
     ws = _instances()
@@ -80,7 +80,9 @@ def test_batch_uneven_instances_vs_alone_and_oracle():
         sig = [torch.zeros(w.M, dtype=torch.float64, device=dev) for w in ws]
         u = [torch.zeros(w.Nx, dtype=torch.float64, device=dev) for w in ws]
         ua = [torch.zeros(w.Nx, dtype=torch.float64, device=dev) for w in ws[:3]]
-        batch = pa.Batch(plans, sig, u, n_streams=4, stream=s)
+        batch = pa.Batch(plans, sig, u, n_streams=4, stream=s, autotune=True,
+                         tune_cache=str(tmp_path / "tiles.json"))
+        print("spread tiles:", [t["tile"] for t in batch.tuning])
         sample_m = {i: set(rng.choice(np.arange(nt - 100, nt + 1), size=3, replace=False).tolist())
                     for i in range(len(ws))}
         got = {i: {} for i in range(len(ws))}
@@ -140,3 +142,51 @@ def test_batch_rejects_bad_arguments():
         pa.Batch([p], [sig], [u[: w.Nx]], stream=s)
     p.set_timing(False)
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_spread_tile_shapes_agree(precision):
+    """Every spreading tile shape computes the same type-1 sums (up to the order of
+    the floating-point additions), so the field after many steps agrees."""
+    import torch
+    import paper_2604_07170_amd as pa
+    from wfp_workloads import config
+    w = config(1)
+    dev = torch.device("cuda", 0)
+    params = w.torch_params(dev)
+    outs = {}
+    for code in (1, 2, 3, 4, 5):
+        plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=precision, interp_order=w.p, spread_tile=code)
+        assert plan.info()["spread_tile"] == code
+        for n in range(1, 61):
+            plan.step(w.sigma_torch(n * w.dt, dev, params))
+        outs[code] = (plan.evaluate().cpu().numpy(), plan.debug(pa.STAGE.S_CUR))
+        plan.close()
+    ref_u, ref_s = outs[3]
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for code, (u, sc) in outs.items():
+        du, ds = rel_l2(u, ref_u), rel_l2(sc, ref_s)
+        print(f"tile {pa.Wfp2d.SPREAD_TILES[code]} {precision}: u {du:.1e}, S_cur {ds:.1e}")
+        assert du <= tol and ds <= tol
+
+
+def test_autotuner_on_a_plan(tmp_path):
+    import torch
+    import paper_2604_07170_amd as pa
+    from paper_2604_07170_amd.autotune import tune_spread
+    from wfp_workloads import config
+    w = config(2)
+    dev = torch.device("cuda", 0)
+    params = w.torch_params(dev)
+    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision="mixed", interp_order=w.p)
+    for n in range(1, 30):
+        plan.step(w.sigma_torch(n * w.dt, dev, params))
+    path = str(tmp_path / "tiles.json")
+    r = tune_spread(plan, reps=5, cache=path)
+    print("tuning", r)
+    assert r["code"] == min(r["ms"], key=r["ms"].get)
+    assert plan.info()["spread_tile"] == r["code"]
+    assert tune_spread(plan, cache=path)["ms"] is None
+    plan.step(w.sigma_torch(30 * w.dt, dev, params))   # stepping continues with the tuned lists
+    torch.cuda.synchronize()
+    plan.close()
