@@ -167,6 +167,52 @@ const char *wfp2d_last_error(wfp2d_plan plan);
 wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t *bytes);
 
 /*
+ * acc[i] += weights[i] * u(x_i, t_m) for the reported step m, instead of
+ * writing u (same stages as wfp2d_evaluate; nothing is added while m < 1).
+ * weights and acc are device pointers to Nx float64 in caller target order,
+ * borrowed for the call.  The adjoint uses it to reduce d(loss)/d(sigma_j(t_l))
+ * against sigma_j(t_l) = A_j s_j(t_l), giving d(loss)/dA_j without storing the
+ * adjoint field.  Errors: ERR_ARG, ERR_STATE, ERR_DEVICE.
+ */
+wfp2d_status wfp2d_evaluate_dot(wfp2d_plan plan, const double *weights, double *acc);
+
+/*
+ * The transpose of a plan's discrete operator.  The map sigma -> u is linear;
+ * its kernel between a source y_j and a target x_i depends on |x_i - y_j| only
+ * (the Green's function, eq. TKdef, the local weights of eq. ul_GL) or on
+ * x_i - y_j through an even Fourier multiplier (the type-1 / type-2 NUFFT
+ * pair with the same even spreading kernel), and it is causal and invariant
+ * under time shifts.  So the transpose is the same method with sources and
+ * targets exchanged, run on time-reversed input: wfp2d_adjoint_init builds
+ * that plan (sources = the forward plan's targets, targets = its sources, the
+ * same dt, W, tol and options; an independent plan, to be destroyed with
+ * wfp2d_destroy).  With forward reports u(t_m), m = 1..T, and input samples
+ * sigma(t_l), l = 1..T + L (L = lookahead), feeding the adjoint plan
+ * x(n) = g(T + L + 1 - n) for n = 1..T + 2L (zero outside 1..T) makes its
+ * report after step n equal to sum_m k(m - l) g(m) at l = T + 2L + 1 - n:
+ * d(loss)/d(sigma(t_l)) for g = d(loss)/du.
+ * Errors: as wfp2d_init; ERR_STATE for a NULL forward plan.
+ */
+wfp2d_status wfp2d_adjoint_init(wfp2d_plan *out, wfp2d_plan forward);
+
+/*
+ * Checkpoints.  The evolving state of a plan (step count, the sigma history
+ * ring, the Fourier rings, the near-history state, alpha_tot and the SOE
+ * state) is copied to or from a caller-owned device buffer of at least
+ * wfp2d_state_bytes bytes (a header, then each buffer on a 256-byte
+ * boundary).  Loading requires a blob from a plan of the same geometry
+ * (M, Nx, number of modes); it replaces the plan's state, including its step
+ * count.  Both synchronise the plan's stream.  Errors: ERR_ARG (NULL, too
+ * small, foreign blob), ERR_STATE, ERR_DEVICE.
+ */
+wfp2d_status wfp2d_state_bytes(wfp2d_plan plan, int64_t *bytes);
+/* Back to zero initial data (eq. wave2d; sigma(t <= 0) = 0): zeroes the
+ * evolving state and the step count; synchronises the plan's stream. */
+wfp2d_status wfp2d_reset(wfp2d_plan plan);
+wfp2d_status wfp2d_save_state(wfp2d_plan plan, void *dst, int64_t bytes);
+wfp2d_status wfp2d_load_state(wfp2d_plan plan, const void *src, int64_t bytes);
+
+/*
  * Graph replay of one plan.  wfp2d_graph_capture records one step followed by
  * one evaluation into a HIP graph, reading the samples from the fixed device
  * pointer sigma [M] and writing u into the fixed device pointer u [Nx]

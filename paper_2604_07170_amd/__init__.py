@@ -85,12 +85,19 @@ def load_library():
                                        ctypes.POINTER(vp), i32, vp]
     lib.wfp2d_batch_launch.argtypes = [vp]
     lib.wfp2d_batch_destroy.argtypes = [vp]
+    lib.wfp2d_evaluate_dot.argtypes = [vp, vp, vp]
+    lib.wfp2d_adjoint_init.argtypes = [ctypes.POINTER(vp), vp]
+    lib.wfp2d_state_bytes.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.wfp2d_reset.argtypes = [vp]
+    lib.wfp2d_save_state.argtypes = [vp, vp, i64]
+    lib.wfp2d_load_state.argtypes = [vp, vp, i64]
     lib.wfp2d_set_spread_tile.argtypes = [vp, i32]
     lib.wfp2d_time_spread.argtypes = [vp, i32, i32, dp]
     for f in ("wfp2d_default_opts", "wfp2d_init", "wfp2d_step", "wfp2d_evaluate", "wfp2d_query", "wfp2d_destroy",
               "wfp2d_debug_copy", "wfp2d_host_eval", "wfp2d_set_timing", "wfp2d_get_timing", "wfp2d_graph_capture",
               "wfp2d_graph_launch", "wfp2d_batch_create", "wfp2d_batch_launch", "wfp2d_batch_destroy",
-              "wfp2d_set_spread_tile", "wfp2d_time_spread"):
+              "wfp2d_set_spread_tile", "wfp2d_time_spread", "wfp2d_evaluate_dot", "wfp2d_adjoint_init",
+              "wfp2d_state_bytes", "wfp2d_save_state", "wfp2d_load_state", "wfp2d_reset"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -134,6 +141,11 @@ class StageNames:
 STAGE = StageNames()
 
 
+class _Handle:
+    def __init__(self, h, device, stream):
+        self.h, self.device, self.stream = h, device, stream
+
+
 class Wfp2d:
     """One plan: sources/targets fixed at construction, one step per sample."""
 
@@ -144,6 +156,12 @@ class Wfp2d:
         import torch
         self._torch = torch
         self.lib = load_library()
+        self._graph_keep = None
+        if isinstance(src_xy, _Handle):              # adopt a plan made by the library (adjoint)
+            self.h, self.device, self.stream = src_xy.h, src_xy.device, src_xy.stream
+            inf = self.info()
+            self.M, self.Nx, self._keep = inf["M"], inf["Nx"], []
+            return
         src = np.ascontiguousarray(np.asarray(src_xy, np.float64).reshape(-1, 2))
         tgt = np.ascontiguousarray(np.asarray(tgt_xy, np.float64).reshape(-1, 2))
         o = Opts()
@@ -193,6 +211,52 @@ class Wfp2d:
             raise ValueError("out must be a contiguous float64 CUDA tensor with Nx elements")
         self._check(self.lib.wfp2d_evaluate(self.h, ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def evaluate_dot(self, weights, acc):
+        """acc += weights * u(t_m) (both float64 CUDA tensors of Nx elements)."""
+        t = self._torch
+        for x in (weights, acc):
+            if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == t.float64 and x.numel() == self.Nx
+                    and x.is_contiguous()):
+                raise ValueError("weights and acc must be contiguous float64 CUDA tensors with Nx elements")
+        self._keep = [weights, acc]
+        self._check(self.lib.wfp2d_evaluate_dot(self.h, ctypes.c_void_p(weights.data_ptr()),
+                                                ctypes.c_void_p(acc.data_ptr())))
+
+    def adjoint(self) -> "Wfp2d":
+        """The plan of the transposed operator (sources and targets exchanged)."""
+        h = ctypes.c_void_p()
+        rc = self.lib.wfp2d_adjoint_init(ctypes.byref(h), self.h)
+        if rc != 0:
+            raise Wfp2dError(rc, self.lib.wfp2d_last_error(None).decode())
+        return Wfp2d(_Handle(h, self.device, self.stream), None, 0.0, 0)
+
+    # -- checkpoints --
+    def reset(self):
+        """Zero initial data again: step count 0, all history cleared."""
+        self._check(self.lib.wfp2d_reset(self.h))
+
+    def state_bytes(self) -> int:
+        n = ctypes.c_int64(0)
+        self._check(self.lib.wfp2d_state_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def save_state(self, buf=None):
+        """Copy the evolving state into a uint8 CUDA tensor (allocated if not given)."""
+        t = self._torch
+        n = self.state_bytes()
+        if buf is None:
+            buf = t.empty(n, dtype=t.uint8, device=self.device)
+        if not (buf.is_cuda and buf.dtype == t.uint8 and buf.numel() >= n and buf.is_contiguous()):
+            raise ValueError("state buffer must be a contiguous uint8 CUDA tensor of state_bytes() bytes")
+        self._check(self.lib.wfp2d_save_state(self.h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
+        return buf
+
+    def load_state(self, buf):
+        t = self._torch
+        if not (buf.is_cuda and buf.dtype == t.uint8 and buf.is_contiguous()):
+            raise ValueError("state buffer must be a contiguous uint8 CUDA tensor")
+        self._check(self.lib.wfp2d_load_state(self.h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
 
     # -- spreading tile shape (autotuned by paper_2604_07170_amd.autotune) --
     SPREAD_TILES = {1: (8, 8), 2: (16, 8), 3: (16, 16), 4: (32, 16), 5: (32, 32)}

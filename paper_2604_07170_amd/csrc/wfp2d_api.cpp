@@ -515,6 +515,14 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_panel_base, LT.panel_base);
     p.d_panel_l2n = p.alloc<int32_t>(p.W);
     upload(p.d_panel_l2n, LT.panel_l2n);
+    p.state_bufs = {{p.d_step, sizeof(int64_t)},
+                    {p.d_sig, (size_t)g.sig_depth * M * sizeof(double)},
+                    {p.d_ring_cur, (size_t)p.W * p.n_modes * 2 * sr},
+                    {p.d_ring_lag, (size_t)p.W * p.n_modes * 2 * sr},
+                    {p.d_D, (size_t)p.n_modes * sizeof(double2)},
+                    {p.d_C, (size_t)p.n_modes * sizeof(double2)},
+                    {p.d_atot, (size_t)p.n_modes * 2 * sr},
+                    {p.d_B, (size_t)p.n_far * kNsoe * sizeof(double2)}};
     hip_check(fft_setup(p), "FFT kernel attributes");
     hip_check(spread_setup(p), "spreading kernel attributes");
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize after set-up");
@@ -537,7 +545,7 @@ static void enqueue_step(Plan &p, const double *sigma)
     timed(p, 6, "far-history update", [&] { return launch_far(p); });
 }
 
-static void enqueue_evaluate(Plan &p, double *u)
+static void enqueue_evaluate(Plan &p, double *u, const double *dot_w = nullptr, double *dot_acc = nullptr)
 {
     timed(p, 7, "fft columns (type 2)", [&] { return launch_fft_cols2(p); });
     timed(p, 8, "fft rows (type 2)", [&] { return launch_fft_rows2(p); });
@@ -546,7 +554,7 @@ static void enqueue_evaluate(Plan &p, double *u)
         hipError_t e = launch_zero_f64(p, p.d_ul, p.Nx);
         return e != hipSuccess ? e : launch_local(p);
     });
-    timed(p, 11, "combine", [&] { return launch_combine(p, u); });
+    timed(p, 11, "combine", [&] { return dot_acc ? launch_combine_dot(p, dot_w, dot_acc) : launch_combine(p, u); });
 }
 
 static void do_step(Plan &p, const double *sigma)
@@ -695,6 +703,9 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
         p.device = o.device;
         p.stream = (hipStream_t)o.stream;
         p.spread_tile = o.spread_tile ? o.spread_tile : 3;
+        p.opts = o;
+        p.h_src_xy.assign(src_xy, src_xy + 2 * M);
+        p.h_tgt_xy.assign(tgt_xy, tgt_xy + 2 * Nx);
         build(p, src_xy, tgt_xy);
         *out = h;
         return WFP2D_OK;
@@ -729,6 +740,128 @@ wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u)
     WFP2D_GUARD(plan, {
         if (!u) fail(WFP2D_ERR_ARG, "NULL u");
         do_evaluate(plan->p, u);
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_evaluate_dot(wfp2d_plan plan, const double *weights, double *acc)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        if (!weights || !acc) fail(WFP2D_ERR_ARG, "NULL weights or acc");
+        Plan &p = plan->p;
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        enqueue_evaluate(p, nullptr, weights, acc);
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_adjoint_init(wfp2d_plan *out, wfp2d_plan forward)
+{
+    if (out) *out = nullptr;
+    if (!out) return WFP2D_ERR_ARG;
+    if (!forward) return WFP2D_ERR_STATE;
+    const Plan &f = forward->p;
+    wfp2d_opts o = f.opts;
+    o.spread_tile = 0;
+    return wfp2d_init(out, f.Nx, f.h_tgt_xy.data(), f.M, f.h_src_xy.data(), f.dt, f.W, f.tol, &o);
+}
+
+// State blob: a header, then the evolving device buffers back to back, each
+// starting on a 256-byte boundary.
+namespace {
+struct StateHeader {
+    uint64_t magic, version, steps, M, Nx, n_modes, n_bufs, bytes;
+};
+constexpr uint64_t kStateMagic = 0x7766703264737461ull;   // "wfp2dsta"
+}  // namespace
+
+static size_t state_layout(const Plan &p, std::vector<size_t> *offs)
+{
+    size_t off = 256;
+    for (const auto &b : p.state_bufs) {
+        if (offs) offs->push_back(off);
+        off += (b.second + 255) / 256 * 256;
+    }
+    return off;
+}
+
+static StateHeader state_header(const Plan &p)
+{
+    StateHeader h{};
+    h.magic = kStateMagic;
+    h.version = 1;
+    h.steps = (uint64_t)p.steps;
+    h.M = (uint64_t)p.M;
+    h.Nx = (uint64_t)p.Nx;
+    h.n_modes = (uint64_t)p.n_modes;
+    h.n_bufs = p.state_bufs.size();
+    h.bytes = state_layout(p, nullptr);
+    return h;
+}
+
+wfp2d_status wfp2d_reset(wfp2d_plan plan)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        for (const auto &b : p.state_bufs)
+            hip_check(launch_zero_f64(p, (double *)b.first, (int64_t)(b.second / sizeof(double))), "reset");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+        p.steps = 0;
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_state_bytes(wfp2d_plan plan, int64_t *bytes)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    if (!bytes) return WFP2D_ERR_ARG;
+    *bytes = (int64_t)state_layout(plan->p, nullptr);
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_save_state(wfp2d_plan plan, void *dst, int64_t bytes)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        std::vector<size_t> offs;
+        const size_t need = state_layout(p, &offs);
+        if (!dst || bytes < (int64_t)need) fail(WFP2D_ERR_ARG, "state buffer NULL or smaller than wfp2d_state_bytes");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        const StateHeader h = state_header(p);
+        hip_check(hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyHostToDevice, p.stream), "state header");
+        for (size_t k = 0; k < p.state_bufs.size(); ++k)
+            hip_check(hipMemcpyAsync((char *)dst + offs[k], p.state_bufs[k].first, p.state_bufs[k].second,
+                                     hipMemcpyDeviceToDevice, p.stream), "state copy");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_load_state(wfp2d_plan plan, const void *src, int64_t bytes)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        std::vector<size_t> offs;
+        const size_t need = state_layout(p, &offs);
+        if (!src || bytes < (int64_t)need) fail(WFP2D_ERR_ARG, "state buffer NULL or smaller than wfp2d_state_bytes");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+        StateHeader h{};
+        hip_check(hipMemcpy(&h, src, sizeof h, hipMemcpyDeviceToHost), "state header");
+        const StateHeader mine = state_header(p);
+        if (h.magic != kStateMagic || h.version != mine.version || h.M != mine.M || h.Nx != mine.Nx ||
+            h.n_modes != mine.n_modes || h.n_bufs != mine.n_bufs || h.bytes != mine.bytes)
+            fail(WFP2D_ERR_ARG, "state blob does not belong to a plan of this geometry");
+        for (size_t k = 0; k < p.state_bufs.size(); ++k)
+            hip_check(hipMemcpyAsync(p.state_bufs[k].first, (const char *)src + offs[k], p.state_bufs[k].second,
+                                     hipMemcpyDeviceToDevice, p.stream), "state copy");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+        p.steps = (int64_t)h.steps;
     });
     return WFP2D_OK;
 }

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/wfp2d.h"
@@ -71,8 +72,8 @@ hipError_t launch_fft_rows2(Plan &p);
 hipError_t launch_interp(Plan &p);
 hipError_t launch_local(Plan &p);
 hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n);
+hipError_t launch_combine_dot(Plan &p, const double *wts, double *acc);
 hipError_t launch_combine(Plan &p, double *u_out);
-hipError_t launch_zero(Plan &p, void *ptr, int64_t bytes);
 
 // ---- the plan ----
 struct Plan {
@@ -162,6 +163,11 @@ struct Plan {
     int32_t dy_base = 0, n_dy = 0;
 
     std::string err;
+
+    // what the plan was made from (to build its transpose) and the evolving state
+    std::vector<double> h_src_xy, h_tgt_xy;          // caller order, [n][2]
+    wfp2d_opts opts{};
+    std::vector<std::pair<void *, size_t>> state_bufs;   // device buffers carried from step to step
 
     // graph replay of one step + evaluation
     hipGraph_t graph = nullptr;

@@ -1081,6 +1081,19 @@ __global__ void k_combine(const double *__restrict__ uh, const double *__restric
     u[i] = uh[s] + ul[s];
 }
 
+// acc[i] += wts[i] * u(x_i, t_m): the field folded into a running weighted sum
+// (used by the adjoint to reduce d(loss)/d(sigma_j(t_l)) against sigma's
+// dependence on source strengths without materialising the field)
+__global__ void k_combine_dot(const double *__restrict__ uh, const double *__restrict__ ul, const int32_t *__restrict__ rank,
+                              const double *__restrict__ wts, double *__restrict__ acc, int64_t Nx,
+                              const int64_t *__restrict__ step, int lookahead)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nx || step[0] - lookahead < 1) return;
+    const int s = rank[i];
+    acc[i] += wts[i] * (uh[s] + ul[s]);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1322,6 +1335,11 @@ hipError_t launch_combine(Plan &p, double *u_out)
     return hipGetLastError();
 }
 
-hipError_t launch_zero(Plan &, void *, int64_t) { return hipSuccess; }
+hipError_t launch_combine_dot(Plan &p, const double *wts, double *acc)
+{
+    hipLaunchKernelGGL(k_combine_dot, dim3(nblk(p.Nx, 256)), dim3(256), 0, p.stream, p.d_uh, p.d_ul, p.d_tgt_rank, wts, acc,
+                       p.Nx, p.d_step, p.lookahead);
+    return hipGetLastError();
+}
 
 }  // namespace wfp2d

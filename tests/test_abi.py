@@ -62,3 +62,16 @@ def test_spread_tile_entry_points_reject_without_a_device():
     o.spread_tile = 0
     o.nufft_tol = 1e-17
     assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.01, 24, 1e-7, ctypes.byref(o)) == -1
+
+
+def test_adjoint_and_state_entry_points_reject_without_a_device():
+    lib = pa.load_library()
+    h = ctypes.c_void_p()
+    n = ctypes.c_int64(0)
+    assert lib.wfp2d_adjoint_init(ctypes.byref(h), None) == -6
+    assert lib.wfp2d_adjoint_init(None, None) == -1
+    assert lib.wfp2d_evaluate_dot(None, None, None) == -6
+    assert lib.wfp2d_state_bytes(None, ctypes.byref(n)) == -6
+    assert lib.wfp2d_save_state(None, None, 0) == -6
+    assert lib.wfp2d_load_state(None, None, 0) == -6
+    assert lib.wfp2d_reset(None) == -6
