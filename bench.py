@@ -67,6 +67,75 @@ def stage_costs(info: dict) -> dict:
     return cost
 
 
+def adjoint_check(args, log):
+    """Backward throughput and a finite-difference check of the strength gradient.
+
+    The workload's sources, targets, time step and signature families, with the
+    signature onsets moved into the first steps so that a short window carries
+    signal: loss = 1/2 sum of u^2 over reported steps m0..nt."""
+    import dataclasses
+    import torch
+    import paper_2604_07170_amd as pa
+    from paper_2604_07170_amd.adjoint import StrengthRun, strength_field
+    from wfp_workloads import config
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = config(args.config)
+    w = dataclasses.replace(w, t0=np.random.default_rng(21).uniform(0.0, 0.02, size=w.M))
+    nt, m0 = 40, 21
+    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=args.precision, interp_order=w.p)
+    la = plan.info()["lookahead"]
+    wu = dataclasses.replace(w, amp=np.ones(w.M))
+    params = wu.torch_params(dev)
+    S = torch.stack([wu.sigma_torch(l * w.dt, dev, params) for l in range(1, nt + la + 1)])
+    run = StrengthRun(plan, lambda l: S[l - 1], nt=nt, m0=m0)
+    A0 = torch.as_tensor(w.amp, dtype=torch.float64, device=dev)
+    A = A0.clone().requires_grad_(True)
+    t0 = time.time()
+    u = strength_field(A, run)
+    L = 0.5 * (u * u).sum()
+    torch.cuda.synchronize()
+    fwd_s = time.time() - t0
+    # backward steps timed with events on the plans' stream (torch's current stream)
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    _ = run.adj                                        # build the transposed plan outside the timed region
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    L.backward()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    bwd_ms = ev0.elapsed_time(ev1)
+    n_adj = nt + 2 * la
+    grad = A.grad.detach().cpu().numpy()
+    log(f"[adjoint] forward {nt + la} steps in {fwd_s:.2f}s; backward {n_adj} steps {bwd_ms:.1f} ms")
+    rng = np.random.default_rng(32)
+    idx = np.sort(rng.choice(w.M, size=args.fd_strengths, replace=False))
+    h = 1.0 if args.precision == "fp64" else float(np.sqrt(w.M))
+    fd = np.zeros(len(idx))
+    t0 = time.time()
+    for k, j in enumerate(idx):
+        e = torch.zeros_like(A0)
+        e[j] = h
+        up = run.forward_field(A0 + e)
+        um = run.forward_field(A0 - e)
+        fd[k] = float(0.5 * ((up * up).sum() - (um * um).sum())) / (2 * h)
+        if k % 8 == 7:
+            log(f"[adjoint] FD {k + 1}/{len(idx)} ({time.time() - t0:.1f}s)")
+    err = float(np.linalg.norm(grad[idx] - fd) / np.linalg.norm(fd))
+    out = {"metric": "adjoint source*steps/s and FD check of d(loss)/d(strengths)",
+           "value": w.M * n_adj / (bwd_ms / 1e3), "unit": "source*steps/s", "n_gpus": 1,
+           "backward_steps": n_adj, "backward_ms_per_step": bwd_ms / n_adj,
+           "precision": args.precision, "workload": w.name + "_onsets_shifted",
+           "loss": "1/2 sum u^2 over reported steps %d..%d" % (m0, nt),
+           "fd": {"strengths": len(idx), "h": h, "rel_l2_adjoint_vs_fd": err,
+                  "grad_norm_fd": float(np.linalg.norm(fd))}}
+    print(json.dumps(out), flush=True)
+    run.close()
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +147,10 @@ def main():
                     help="targets of the CPU oracle sample (at the last timed step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default spreading tile shape")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead: time the adjoint (backward) steps and check d(loss)/d(strengths) by central "
+                         "finite differences on 32 strengths, on the workload's geometry over a short window")
+    ap.add_argument("--fd-strengths", type=int, default=32)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a device-to-device copy of this many GiB (calibrates HBM byte counters)")
@@ -104,6 +177,9 @@ def main():
     from wfp_workloads import config
 
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    if args.adjoint:
+        adjoint_check(args, log)
+        return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     w = config(args.config)

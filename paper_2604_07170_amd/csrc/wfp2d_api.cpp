@@ -286,8 +286,9 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         far_cls[f] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), far_key[f]) - keys.begin());
 
     // ---------------- geometry: sort by local cell ----------------
-    // cells of side >= delta/2: every target within delta of a source lies in the 5 x 5 block of cells around it
-    p.ncell = std::max(1, (int)std::floor(4.0 / p.delta));
+    // cells of side >= delta/2 (the 5 x 5 block then covers every pair with r < delta); larger cells are
+    // also correct, so the count is capped to keep the cell tables small
+    p.ncell = std::max(1, std::min(8192, (int)std::floor(4.0 / p.delta)));
     p.cell_h = 2.0 / p.ncell;
     auto cell_of = [&](double x, double y) {
         int cx = std::min(p.ncell - 1, std::max(0, (int)std::floor((x + 1.0) / p.cell_h)));

@@ -778,13 +778,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, const int6
     __shared__ int qn;
     __shared__ int rbeg[5], rcum[6];
 
-    const int cell = blockIdx.x, n = A.ncell;
-    const int cx = cell % n, cy = cell / n;
-    const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
-    if (s0 == s1) return;                       // uniform: no sources in this cell
+    const int n = A.ncell;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const int nlev = g.nlev, nreg = A.n_reg, D = kChebDeg;
     const double d2 = A.delta * A.delta;
+    // grid-stride over source cells (a dispatch is limited to 2^32 work-items)
+    for (int cell = blockIdx.x; cell < n * n; cell += gridDim.x) {
+    const int cx = cell % n, cy = cell / n;
+    const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
+    if (s0 == s1) continue;                     // uniform: no sources in this cell
 
     // the 5 x 5 block of target cells: up to 5 contiguous runs of sorted targets
     if (tid == 0) {
@@ -912,6 +914,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, const int6
 #pragma unroll
         for (int j = 0; j < kLocalOwn; ++j)
             if (tg[j] >= 0 && acc[j] != 0.0) unsafeAtomicAdd(&A.ul[tg[j]], acc[j]);
+    }
+    __syncthreads();                            // rbeg / rcum are rewritten for the next cell
     }
 }
 
@@ -1061,10 +1065,12 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
     }
 }
 
+// Grid-stride fill: a dispatch covers at most 2^32 work-items, and the sigma
+// ring alone can exceed that (4.3e9 doubles at 10^6 sources).
 __global__ void k_zero_f64(double *__restrict__ p, int64_t n)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
 }
 
 // u (caller order) = u_h + u_l, or zeros before the first reported step
@@ -1318,13 +1324,15 @@ hipError_t launch_local(Plan &p)
             hipLaunchKernelGGL(k_local_fast<43>, dim3(grid), dim3(threads), 0, p.stream, A, p.d_step, p.g);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_local, dim3((unsigned)(p.ncell * p.ncell)), dim3(kLocalThreads), 0, p.stream, A, p.d_step, p.g);
+    hipLaunchKernelGGL(k_local, dim3((unsigned)std::min<int64_t>((int64_t)p.ncell * p.ncell, 65536)), dim3(kLocalThreads), 0,
+                       p.stream, A, p.d_step, p.g);
     return hipGetLastError();
 }
 
 hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n)
 {
-    hipLaunchKernelGGL(k_zero_f64, dim3(nblk(n, 256)), dim3(256), 0, p.stream, ptr, n);
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n, 256), 1), 65536)), dim3(256), 0,
+                       p.stream, ptr, n);
     return hipGetLastError();
 }
 

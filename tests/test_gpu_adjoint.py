@@ -234,3 +234,33 @@ def test_state_save_load_and_reset():
     assert rel_l2(d[-10:], e[-10:]) <= 1e-14
     for p in (plan, twin, other, fresh):
         p.close()
+
+
+def test_reset_clears_a_history_ring_beyond_2_32_elements():
+    """At 10^6 sources the sigma ring holds 4.3e9 doubles, more than one dispatch
+    of one work-item per element can cover: after a reset, a rerun must match the
+    run of the freshly allocated plan (whose memory the allocator zeroed)."""
+    import torch
+    from wfp_workloads import config
+    w = config(4)
+    dev = torch.device("cuda", 0)
+    plan = _plan(w, "mixed")
+    info = plan.info()
+    assert info["sigma_depth"] * w.M > 2**32
+    j = int(np.random.default_rng(4).integers(w.M))
+    x = torch.as_tensor(np.random.default_rng(3).standard_normal(40), device=dev)
+
+    def run():
+        plan.reset()
+        e = torch.zeros(w.M, dtype=torch.float64, device=dev)
+        for n in range(1, 25):
+            e.zero_()
+            e[j] = x[n - 1]
+            plan.step(e)
+        return plan.evaluate().cpu().numpy(), plan.debug(2)      # u and the lag transform S_lag
+
+    u0, lag0 = run()
+    u1, lag1 = run()
+    assert np.abs(lag1).max() <= 1e-6 * max(np.abs(lag0).max(), 1.0)   # sigma(t <= 0) = 0 behind the lag
+    assert rel_l2(u1, u0) <= 1e-13
+    plan.close()
