@@ -33,6 +33,32 @@ PEAK_FP64_TFLOPS = 78.6        # vector FP64
 PEAK_FP32_TFLOPS = 157.3       # vector FP32
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (read + written) from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, scaled by its copy-kernel calibration; None when the
+    summary is missing, does not list the kernel, or was taken on another kernels source."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_counters_cfg4_M1e6_mixed.md")
+    src = os.path.join(ROOT, "paper_2604_07170_amd", "csrc", "wfp2d_kernels.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"sha256 prefix: ([0-9a-f]{16})", text)
+    if not m or m.group(1) != digest:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+        if len(cells) == 4 and cells[0].split("<")[0].endswith(kernel):
+            try:
+                return int(round((float(cells[2]) + float(cells[3])) * 1e6))
+            except ValueError:
+                return None
+    return None
+
+
 def stage_costs(info: dict) -> dict:
     """Algorithmic work of one launch of each stage: (bound, amount, unit).
 
@@ -259,9 +285,11 @@ def main():
     if d["bound"] == "hbm":
         roof = {"bound": "hbm", "kernel": pa.Wfp2d.KERNELS[pa.Wfp2d.STAGES.index(dom)], "achieved": d["achieved_GBs"],
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": d["frac"], "traffic": None}
+        roof["traffic"] = measured_traffic(roof["kernel"])
     else:
         roof = {"bound": "alu", "kernel": pa.Wfp2d.KERNELS[pa.Wfp2d.STAGES.index(dom)], "achieved": d["achieved_TFLOPs"],
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": d["frac"], "traffic": None}
+        roof["traffic"] = measured_traffic("k_local_fast" if roof["kernel"] == "k_local" else roof["kernel"])
     hbm_bytes = sum(costs[s][1] for s in per_stage if costs[s][0] == "hbm")
     step_hbm_frac = hbm_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS
 

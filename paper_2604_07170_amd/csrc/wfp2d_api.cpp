@@ -525,7 +525,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
                     {p.d_atot, (size_t)p.n_modes * 2 * sr},
                     {p.d_B, (size_t)p.n_far * kNsoe * sizeof(double2)}};
     hip_check(fft_setup(p), "FFT kernel attributes");
-    hip_check(spread_setup(p), "spreading kernel attributes");
+    hip_check(kernel_setup(p), "local kernel attributes");
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize after set-up");
 }
 

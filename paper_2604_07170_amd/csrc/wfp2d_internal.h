@@ -60,7 +60,7 @@ struct Plan;
 hipError_t launch_step_begin(Plan &p);
 hipError_t launch_ingest(Plan &p, const double *sigma_in);
 hipError_t launch_spread(Plan &p);
-hipError_t spread_setup(Plan &p);
+hipError_t kernel_setup(Plan &p);
 hipError_t fft_setup(Plan &p);
 hipError_t launch_fft_rows1(Plan &p);
 hipError_t launch_fft_cols1(Plan &p);

@@ -920,32 +920,107 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(LocalArgs A, const int6
 }
 
 // ---------------------------------------------------------------------------
-// Local part, fast form (one sub-panel per time-step panel, NL sigma levels):
-// a persistent kernel in which thread e holds row e = (sub-panel P, Chebyshev
-// index c) of the coefficient table C_{P,c,d} in registers for its lifetime,
-// so the per-source profile coefficients psi_{j,P,c} = sum_d C_{P,c,d} sigma_{j,d}
-// of every source cell need only sigma from LDS.  The sub-panel of a pair is
-// its time-step panel k = floor(r/dt) and the Chebyshev coordinate is
-// x = 2 sqrt((k+1) dt - r) / u_a - 1, both computed arithmetically.
+// Local part, fast form (one sub-panel per time-step panel, NL sigma levels).
+// Persistent over source cells.  Thread e holds row e = (sub-panel P,
+// Chebyshev index c) of the coefficient table C_{P,c,d} in registers, so the
+// per-source profile coefficients psi_{j,P,c} = sum_d C_{P,c,d} sigma_{j,d} of
+// a chunk of sources need only sigma from LDS.  Pairs are then found and
+// evaluated in two decoupled passes per wave:
+//   filter:  candidates (source, target) of the chunk x target batch, one per
+//            lane, tested on r^2 alone; hits are compacted into a wave-private
+//            LDS ring (ballot + prefix count);
+//   evaluate: whenever 128 hits are pending, every lane takes two of them:
+//            panel k = floor(r/dt), coordinate x = 2 sqrt((k+1) dt - r)/u_a - 1,
+//            two interleaved Clenshaw sums of the source's profile on panel k,
+//            added to per-target sums in LDS.
+// So the Clenshaw work runs on full waves of true neighbours only.  Pairs with
+// r < dt/2 (dyadic sub-panels) go to a workgroup queue, one wave per pair.
+// Per-target sums are added to u_l with one FP64 atomic per (target, cell).
 // ---------------------------------------------------------------------------
+constexpr int kFastTB = 512;     // targets per batch (their positions and sums in LDS)
+constexpr int kFastRing = 192;   // per-wave ring of pending hits (>= 128 + 64)
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// panel and Chebyshev coordinate of a regular pair (r >= dt/2)
+__device__ __forceinline__ int fast_panel(const LocalArgs &A, double r, int W, double dt, double &x)
+{
+    const int k = min((int)(r * A.inv_dt), W - 1);
+    x = fmin(1.0, fmax(-1.0, sqrt(fmax(0.0, (k + 1) * dt - r)) * (k ? A.two_over_ua : A.two_over_ua0) - 1.0));
+    return k;
+}
+
+// psi layout in LDS: row (source q, panel k) at q * psiSrc + k * kPsiRow, with the
+// row stride padded to 21 doubles and the source stride to 16 * 21 + 1, so that
+// lanes reading different panels (and sources) spread over the LDS banks.
+constexpr int kPsiRow = kChebDeg + 1;
+constexpr int kFastRB = 4;       // 16-row blocks of the coefficient table per wave (rows <= 64 per wave)
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int psi_src_stride(int n_reg) { return n_reg * kPsiRow + 1; }
+
 template <int NL>
 __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int64_t *__restrict__ step, Geom g)
 {
     const int64_t m = step[0] - g.lookahead;
-    __shared__ double psi[kFastSrc * kFastRow];   // [source][row]
+    extern __shared__ double fast_lds[];              // psi [kFastSrc][psiSrc], then the hit rings
     __shared__ double sigs[kFastSrc * NL];
     __shared__ double2 spos[kFastSrc];
+    __shared__ double2 tpos[kFastTB];
+    __shared__ double tacc[kFastTB];
+    __shared__ int tglob[kFastTB];
     __shared__ int qs[kLocalQueue], qt[kLocalQueue];
     __shared__ double qr[kLocalQueue];
     __shared__ int qn;
     __shared__ int rbeg[5], rcum[6];
 
     const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = bd >> 6;
-    const int n = A.ncell, D = kChebDeg, nrow = A.n_reg * kChebDeg;
-    const double d2 = A.delta * A.delta, dt = g.dt;
-    double cr[NL];
-#pragma unroll
-    for (int d = 0; d < NL; ++d) cr[d] = tid < nrow ? A.creg[(size_t)tid * NL + d] : 0.0;
+    const int n = A.ncell, D = kChebDeg, nrow = A.n_reg * kChebDeg, psiSrc = psi_src_stride(A.n_reg);
+    const double d2 = A.delta * A.delta, dt = g.dt, q2 = 0.25 * dt * dt;
+    double *psi = fast_lds;
+    double *ring_r2 = fast_lds + kFastSrc * psiSrc + wave * kFastRing;
+    uint32_t *ring_ts = reinterpret_cast<uint32_t *>(fast_lds + kFastSrc * psiSrc + nwave * kFastRing) + wave * kFastRing;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes below this one
+    // psi = C sigma as FP64 MFMA 16x16x4 tiles: this wave owns row blocks rb = wave + j nwave
+    // (16 table rows each); its A operands C[rb*16 + lane%16][4 ks + lane/16] are read from
+    // the (L2-resident) table for each chunk, so they occupy registers only in that phase.
+    constexpr int KS = (NL + 3) / 4;
+    const int nblk = (nrow + 15) / 16;
+
+    // targets kk in [tb0, tb0 + ntb) of the current 5 x 5 block -> LDS
+    auto load_batch = [&](int tb0, int ntb) {
+        for (int t = tid; t < ntb; t += bd) {
+            const int kk = tb0 + t;
+            int r = 0;
+            while (r < 4 && kk >= rcum[r + 1]) ++r;
+            const int tg = rbeg[r] + (kk - rcum[r]);
+            tglob[t] = tg;
+            tpos[t] = A.txy[tg];
+            tacc[t] = 0.0;
+        }
+    };
+    auto flush_batch = [&](int ntb) {
+        for (int t = tid; t < ntb; t += bd)
+            if (tacc[t] != 0.0) unsafeAtomicAdd(&A.ul[tglob[t]], tacc[t]);
+    };
+    // evaluate ring entries [h, h + 128) of this wave (those at or beyond `cnt` are padding)
+    auto evaluate = [&](int h, int cnt) {
+        const int e0 = h + lane, e1 = h + 64 + lane;
+        const bool v0 = e0 < cnt, v1 = e1 < cnt;
+        const int p0 = e0 % kFastRing, p1 = e1 % kFastRing;
+        const uint32_t w0 = v0 ? ring_ts[p0] : 0u, w1 = v1 ? ring_ts[p1] : 0u;
+        const double r0 = v0 ? sqrt(ring_r2[p0]) : dt, r1 = v1 ? sqrt(ring_r2[p1]) : dt;
+        double x0, x1, u0, u1;
+        const int k0 = fast_panel(A, r0, g.W, dt, x0), k1 = fast_panel(A, r1, g.W, dt, x1);
+        cheb_eval2(psi + (int)(w0 >> 16) * psiSrc + k0 * kPsiRow, x0, psi + (int)(w1 >> 16) * psiSrc + k1 * kPsiRow, x1,
+                   u0, u1);
+        if (v0) atomicAdd(&tacc[w0 & 0xffffu], u0);
+        if (v1) atomicAdd(&tacc[w1 & 0xffffu], u1);
+    };
 
     for (int cell = blockIdx.x; cell < n * n; cell += gridDim.x) {
         const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
@@ -968,81 +1043,108 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
         }
         __syncthreads();
         const int NT = rcum[5];
-        for (int tc0 = 0; tc0 < NT; tc0 += kFastOwn * bd) {
-            const int nown = min(kFastOwn, (NT - tc0 + bd - 1) / bd);
-            int tg[kFastOwn];
-            double2 x[kFastOwn];
-            double acc[kFastOwn];
+        const bool single = NT <= kFastTB;        // all targets stay in LDS for the whole cell
+        if (single) load_batch(0, NT);
+        for (int sb = s0; sb < s1; sb += kFastSrc) {
+            const int ns = min(kFastSrc, s1 - sb);
+            for (int e = tid; e < ns * NL; e += bd) {
+                const int sidx = e / NL, d = e - sidx * NL;
+                sigs[e] = A.sig[sig_slot(m, d, g) * g.M + sb + sidx];
+            }
+            if (tid < ns) spos[tid] = A.sxy[sb + tid];
+            {
+                // A operands of this wave's row blocks: issued before the barrier so that their
+                // latency overlaps the sigma loads
+                double ca[kFastRB][KS];
 #pragma unroll
-            for (int j = 0; j < kFastOwn; ++j) {
-                const int kk = tc0 + tid + j * bd;
-                tg[j] = -1;
-                x[j] = make_double2(1e30, 1e30);
-                acc[j] = 0.0;
-                if (j < nown && kk < NT) {
-                    int r = 0;
-                    while (r < 4 && kk >= rcum[r + 1]) ++r;
-                    tg[j] = rbeg[r] + (kk - rcum[r]);
-                    x[j] = A.txy[tg[j]];
+                for (int j = 0; j < kFastRB; ++j) {
+                    const int row = (wave + j * nwave) * 16 + (lane & 15);
+                    const double *__restrict__ crow = A.creg + (size_t)min(row, nrow - 1) * NL;
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int d = 4 * ks + (lane >> 4);
+                        ca[j][ks] = (row < nrow && d < NL) ? crow[d] : 0.0;
+                    }
+                }
+                __syncthreads();
+                mfma_d4 acc[kFastRB];
+#pragma unroll
+                for (int j = 0; j < kFastRB; ++j) acc[j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+                const int q = lane & 15;
+#pragma unroll
+                for (int j = 0; j < kFastRB; ++j) {
+                    const int rb = wave + j * nwave;
+                    if (rb >= nblk) continue;              // uniform across the wave
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int d = 4 * ks + (lane >> 4);
+                        const double b = (q < ns && d < NL) ? sigs[q * NL + d] : 0.0;   // B[d][q] = sigma_{q,d}
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[j][ks], b, acc[j], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kFastRB; ++j) {
+                    const int rb = wave + j * nwave;
+                    if (rb >= nblk || q >= ns) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rb * 16 + (lane >> 4) + 4 * r;   // D[lane][r] = C[lane/16 + 4 r][lane%16]
+                        if (row < nrow) psi[q * psiSrc + (row / D) * kPsiRow + row % D] = acc[j][r];
+                    }
                 }
             }
-            for (int sb = s0; sb < s1; sb += kFastSrc) {
-                const int ns = min(kFastSrc, s1 - sb);
-                for (int e = tid; e < ns * NL; e += bd) {
-                    const int sidx = e / NL, d = e - sidx * NL;
-                    sigs[e] = A.sig[sig_slot(m, d, g) * g.M + sb + sidx];
-                }
-                if (tid < ns) spos[tid] = A.sxy[sb + tid];
+            for (int tb0 = 0; tb0 < NT; tb0 += kFastTB) {
+                const int ntb = min(kFastTB, NT - tb0);
+                if (!single) load_batch(tb0, ntb);
                 if (tid == 0) qn = 0;
                 __syncthreads();
-                if (tid < nrow) {
-                    for (int q = 0; q < ns; ++q) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int d = 0; d < NL; ++d) v = fma(cr[d], sigs[q * NL + d], v);
-                        psi[q * nrow + tid] = v;
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < kFastOwn; ++j) {
-                    if (j >= nown) continue;
-                    const double2 xj = x[j];
-                    for (int sidx = 0; sidx < ns; sidx += 2) {
-                        const bool two = sidx + 1 < ns;
-                        const int s2 = two ? sidx + 1 : sidx;
-                        const double2 y0 = spos[sidx], y1 = spos[s2];
-                        const double ax = xj.x - y0.x, ay = xj.y - y0.y, bx = xj.x - y1.x, by = xj.y - y1.y;
-                        const double ra2 = ax * ax + ay * ay, rb2 = bx * bx + by * by;
-                        bool ha = ra2 > 0.0 && ra2 < d2, hb = two && rb2 > 0.0 && rb2 < d2;
-                        if (!(ha || hb)) continue;
-                        const double ra = sqrt(ra2), rb = sqrt(rb2);
-                        const double rra = ra * A.inv_dt, rrb = rb * A.inv_dt;
-                        if ((ha && rra < 0.5) || (hb && rrb < 0.5)) {   // rare: queue, evaluated level by level
-                            const bool qa = ha && rra < 0.5, qb = hb && rrb < 0.5;
-                            int qq = atomicAdd(&qn, (qa ? 1 : 0) + (qb ? 1 : 0));
-                            if (qa) {
-                                if (qq < kLocalQueue) { qs[qq] = sidx; qt[qq] = tg[j]; qr[qq] = ra; }
-                                else acc[j] += dyadic_direct(A, sigs + sidx * NL, NL, ra, rra);
-                                ++qq;
-                                ha = false;
+                // filter (source-major: lanes over targets) + compaction + evaluation, per wave
+                int head = 0, cnt = 0;                  // wave-uniform ring counters
+                const int ntb64 = (ntb + 63) >> 6;      // 64-target blocks per source
+                for (int blk = wave; blk < ns * ntb64; blk += nwave) {   // (source, target block) round robin
+                    const int sidx = blk / ntb64;
+                    const double2 y = spos[sidx];
+                    {
+                        const int t = (blk - sidx * ntb64) * 64 + lane;
+                        bool hit = false;
+                        double r2 = 0.0;
+                        if (t < ntb) {
+                            const double2 x = tpos[t];
+                            const double dx = x.x - y.x, dy = x.y - y.y;
+                            r2 = dx * dx + dy * dy;
+                            hit = r2 > 0.0 && r2 < d2;
+                            if (hit && r2 < q2) {       // r < dt/2: dyadic sub-panels
+                                hit = false;
+                                const int q = atomicAdd(&qn, 1);
+                                const double r = sqrt(r2);
+                                if (q < kLocalQueue) {
+                                    qs[q] = sidx;
+                                    qt[q] = t;
+                                    qr[q] = r;
+                                } else {
+                                    atomicAdd(&tacc[t], dyadic_direct(A, sigs + sidx * NL, NL, r, r * A.inv_dt));
+                                }
                             }
-                            if (qb) {
-                                if (qq < kLocalQueue) { qs[qq] = s2; qt[qq] = tg[j]; qr[qq] = rb; }
-                                else acc[j] += dyadic_direct(A, sigs + s2 * NL, NL, rb, rrb);
-                                hb = false;
-                            }
-                            if (!(ha || hb)) continue;
                         }
-                        const int ka = min((int)rra, g.W - 1), kb = min((int)rrb, g.W - 1);
-                        const double xa = ha ? fmin(1.0, fmax(-1.0, sqrt(fmax(0.0, (ka + 1) * dt - ra)) * (ka ? A.two_over_ua : A.two_over_ua0) - 1.0)) : 0.0;
-                        const double xb = hb ? fmin(1.0, fmax(-1.0, sqrt(fmax(0.0, (kb + 1) * dt - rb)) * (kb ? A.two_over_ua : A.two_over_ua0) - 1.0)) : 0.0;
-                        double va, vb;
-                        cheb_eval2(psi + sidx * nrow + (ha ? ka : 0) * D, xa, psi + s2 * nrow + (hb ? kb : 0) * D, xb, va, vb);
-                        acc[j] += (ha ? va : 0.0) + (hb ? vb : 0.0);
+                        const uint64_t mask = __ballot(hit);
+                        if (hit) {
+                            const int pos = (cnt + __popcll(mask & below)) % kFastRing;
+                            ring_ts[pos] = (uint32_t)t | ((uint32_t)sidx << 16);
+                            ring_r2[pos] = r2;
+                        }
+                        cnt += __popcll(mask);
+                        if (cnt - head >= 128) {
+                            wave_sync();
+                            evaluate(head, cnt);
+                            head += 128;
+                            wave_sync();
+                        }
                     }
                 }
+                wave_sync();
+                for (; head < cnt; head += 128) evaluate(head, cnt);
                 __syncthreads();
+                // queued pairs with r < dt/2: one wavefront per pair, lanes over levels
                 const int nq = min(qn, kLocalQueue);
                 for (int q = wave; q < nq; q += nwave) {
                     const int sidx = qs[q];
@@ -1053,15 +1155,19 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
                     for (int d = lane; d < NL; d += 64)
                         v = fma(cheb_eval(A.cheb + ((size_t)sub * NL + d) * D, xc), sigs[sidx * NL + d], v);
                     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-                    if (lane == 0) unsafeAtomicAdd(&A.ul[qt[q]], v);
+                    if (lane == 0) atomicAdd(&tacc[qt[q]], v);
                 }
                 __syncthreads();
+                if (!single) {
+                    flush_batch(ntb);
+                    __syncthreads();
+                }
             }
-#pragma unroll
-            for (int j = 0; j < kFastOwn; ++j)
-                if (tg[j] >= 0 && acc[j] != 0.0) unsafeAtomicAdd(&A.ul[tg[j]], acc[j]);
         }
-        __syncthreads();
+        if (single) {
+            flush_batch(NT);
+            __syncthreads();
+        }
     }
 }
 
@@ -1149,7 +1255,16 @@ hipError_t launch_spread(Plan &p)
     return p.precision == WFP2D_PREC_MIXED ? spread_typed<float>(p) : spread_typed<double>(p);
 }
 
-hipError_t spread_setup(Plan &) { return hipSuccess; }
+// dynamic LDS of the fast local kernel: up to kFastRow rows x kFastSrc sources of
+// profile coefficients plus one hit ring per wave
+hipError_t kernel_setup(Plan &)
+{
+    const int bytes = kFastSrc * (kFastRow / kChebDeg * (kChebDeg + 1) + 1) * (int)sizeof(double) +
+                      (kFastRow / 64) * kFastRing * 12;
+    hipError_t e = hipFuncSetAttribute((const void *)k_local_fast<35>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_local_fast<43>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
 
 static size_t fft_lds_bytes(const Plan &p) { return (size_t)(p.g.Q + p.g.Q / 16) * 2 * p.sizeof_real; }
 
@@ -1318,10 +1433,12 @@ hipError_t launch_local(Plan &p)
         const unsigned threads = (unsigned)((nrow + 63) / 64 * 64);
         const int cells = p.ncell * p.ncell;
         const unsigned grid = (unsigned)std::min(cells, 2 * 256);
+        const size_t lds = (size_t)kFastSrc * (p.n_reg * (kChebDeg + 1) + 1) * sizeof(double) +
+                           (size_t)(threads / 64) * kFastRing * 12;
         if (p.g.nlev == 35)
-            hipLaunchKernelGGL(k_local_fast<35>, dim3(grid), dim3(threads), 0, p.stream, A, p.d_step, p.g);
+            hipLaunchKernelGGL(k_local_fast<35>, dim3(grid), dim3(threads), lds, p.stream, A, p.d_step, p.g);
         else
-            hipLaunchKernelGGL(k_local_fast<43>, dim3(grid), dim3(threads), 0, p.stream, A, p.d_step, p.g);
+            hipLaunchKernelGGL(k_local_fast<43>, dim3(grid), dim3(threads), lds, p.stream, A, p.d_step, p.g);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_local, dim3((unsigned)std::min<int64_t>((int64_t)p.ncell * p.ncell, 65536)), dim3(kLocalThreads), 0,
