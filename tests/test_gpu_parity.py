@@ -96,3 +96,41 @@ def test_single_source_radial_symmetry():
         assert np.abs(u - u.mean()).max() <= 1e-8 * max(np.abs(u).max(), 1e-12)
     Uo = oracle_field(w, plan.info(), np.arange(len(tgt)), [30, 60], self_mode=0)
     assert rel_l2(np.array([us[30], us[60]]).T, Uo) <= TOL_E2E
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config1_star_curve_sampled(precision):
+    """4096 points on the star curve, 20 wavelengths, 2000 steps: 32 seeded targets x
+    20 steps spread over the run (the far history is active from step LA + W)."""
+    from wfp_workloads import config
+    w = config(1)
+    steps = list(range(50, w.nt + 1, 100))
+    plan, us = run_plan(w, precision, record=set(steps))
+    info = plan.info()
+    tg = np.sort(np.random.default_rng(11).choice(w.Nx, size=32, replace=False))
+    U = np.array([us[s][tg] for s in steps]).T
+    Uo = oracle_field(w, info, tg, steps)
+    err = rel_l2(U, Uo)
+    late = [k for k, s in enumerate(steps) if s > info["LA"] + info["W"]]
+    err_late = np.linalg.norm(U[:, late] - Uo[:, late]) / np.linalg.norm(Uo)
+    print(f"config1 {precision}: rel L2 {err:.3e} over {U.size} samples; far-history steps contribute "
+          f"{err_late:.1e} (relative to the whole sample), LA = {info['LA']}")
+    assert err <= TOL_E2E
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config2_sampled_with_far_history(precision):
+    """65536 uniform sources, 100 wavelengths: 8 seeded targets x 3 steps after the
+    far-history onset (LA = 1596), the signatures having started at t >= 2.25."""
+    from wfp_workloads import config
+    w = config(2)
+    steps = [1700, 1750, 1800]
+    plan, us = run_plan(w, precision, nsteps=max(steps), record=set(steps))
+    info = plan.info()
+    assert max(steps) > info["LA"] + info["W"]
+    tg = np.sort(np.random.default_rng(12).choice(w.Nx, size=8, replace=False))
+    U = np.array([us[s][tg] for s in steps]).T
+    Uo = oracle_field(w, info, tg, steps)
+    err = rel_l2(U, Uo)
+    print(f"config2 {precision}: rel L2 {err:.3e} over {U.size} samples (|u| ~ {np.abs(Uo).max():.2f})")
+    assert err <= TOL_E2E
