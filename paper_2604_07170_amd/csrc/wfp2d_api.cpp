@@ -451,7 +451,11 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     p.d_T1t = p.alloc<char>((int64_t)g.Lpad * N * 2 * sr);
     p.d_F = p.alloc<char>(N * N * 2 * sr);
     p.d_corr = upload_real(p, corr);
-    p.d_tw = upload_real(p, tw);
+    {
+        double *d = p.alloc<double>((int64_t)tw.size());   // FP64 in both forms: staged into LDS tables
+        upload(d, tw);
+        p.d_tw = d;
+    }
     p.d_ring_cur = p.alloc<char>((int64_t)p.W * p.n_modes * 2 * sr);
     p.d_ring_lag = p.alloc<char>((int64_t)p.W * p.n_modes * 2 * sr);
     p.d_chunks = p.alloc<ModeChunk>(p.n_chunks);

@@ -124,7 +124,7 @@ struct Plan {
     void *d_T1t = nullptr;            // [N][Lpad] its transpose
     void *d_F = nullptr;              // [N][N] complex Real, index [nx+R][ny+R]
     void *d_corr = nullptr;           // [N] complex Real: e^{2 pi i n lmin/nf} / psi_hat(n)
-    void *d_tw = nullptr;             // [nf] complex Real: e^{2 pi i j / nf}
+    void *d_tw = nullptr;             // [nf] complex float64: e^{2 pi i j / nf}
     // rings of Fourier coefficients
     void *d_ring_cur = nullptr;       // [W][n_modes] complex Real
     void *d_ring_lag = nullptr;       // [W][n_modes] complex Real

@@ -143,17 +143,37 @@ __global__ __launch_bounds__(64) void k_spread(const double *__restrict__ sig, c
 // Each thread holds 16 values; Stockham passes of radix 16 run in registers
 // with one LDS exchange per pass, and a last pass of radix 2, 4 or 8 covers
 // L mod 4.  sign = +1 computes X[k] = sum_m x[m] e^{+2 pi i k m/Q}, sign = -1
-// the conjugate kernel.  Twiddles come from tw[j] = e^{2 pi i j/nf}, nf = P Q.
+// the conjugate kernel.  Twiddles e^{2 pi i j/nf} (nf = P Q) come from the
+// workgroup's two-level LDS table (tw_at).
 // The LDS index is padded by one element every 16 against bank conflicts.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
+// Twiddles e^{2 pi i j/nf}, j in [0, nf), from a two-level FP64 table in LDS (staged
+// once per workgroup by tw_stage): tt[j & 63] * tt[64 + (j >> 6)], formed in FP64 and
+// rounded once to the working precision.  Gathers from a global table go through L2
+// at random strides and cost about half of the transform time.
 template <class C>
-__device__ __forceinline__ C twid(const C *__restrict__ tw, int idx, int sign)
+__device__ __forceinline__ C tw_at(const double2 *tt, int j)
 {
-    C t = tw[idx];
+    const double2 a = tt[64 + (j >> 6)], b = tt[j & 63];
+    using R = decltype(C{}.x);
+    return C{(R)(a.x * b.x - a.y * b.y), (R)(a.x * b.y + a.y * b.x)};
+}
+
+template <class C>
+__device__ __forceinline__ C twid(const double2 *tt, int idx, int sign)
+{
+    C t = tw_at<C>(tt, idx);
     if (sign < 0) t.y = -t.y;
     return t;
+}
+
+// stage the two-level table of e^{2 pi i j/nf} (from the global FP64 table tw) into tt
+__device__ __forceinline__ void tw_stage(double2 *tt, const double2 *__restrict__ tw, int nf)
+{
+    for (int i = threadIdx.x; i < 64 + nf / 64; i += blockDim.x) tt[i] = tw[i < 64 ? i : (i - 64) * 64];
+    __syncthreads();
 }
 
 // multiply by sign*i
@@ -239,7 +259,7 @@ template <class C> __device__ __forceinline__ void dft16(C *v, int sign)
 
 // last Stockham pass of radix R in {2, 4, 8}: each thread does 16/R butterflies
 template <int R, class C>
-__device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int Ns, int sign, const C *__restrict__ tw, int P)
+__device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int Ns, int sign, const double2 *tw, int P)
 {
     constexpr int nb = 16 / R;
     const int tid = threadIdx.x, T = Q >> 4, QR = Q / R;
@@ -253,7 +273,7 @@ __device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int Ns, int sign,
     for (int i = 0; i < nb; ++i) {
         const int j = tid + T * i, k = j % Ns;
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], twid(tw, k * r * stride, sign));
+        for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], twid<C>(tw, k * r * stride, sign));
         if (R == 2) dft2(v[i * R], v[i * R + 1]);
         else if (R == 4) dft4(v[i * R], v[i * R + 1], v[i * R + 2], v[i * R + 3], sign);
         else dft8(v + i * R, sign);
@@ -267,7 +287,7 @@ __device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int Ns, int sign,
 // One workgroup transforms one line.  v[r] (r < 16) holds x[tid + r Q/16] on
 // entry; the result is left in lds (natural order, padded index).
 template <class C>
-__device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const C *__restrict__ tw, int P)
+__device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const double2 *tw, int P)
 {
     const int tid = threadIdx.x, T = Q >> 4;
     // first radix-16 pass (Ns = 1): no twiddles
@@ -282,7 +302,7 @@ __device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const C *__restri
         __syncthreads();
         const int k = tid % Ns, stride = (Q / (16 * Ns)) * P;
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twid(tw, k * r * stride, sign));
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twid<C>(tw, k * r * stride, sign));
         dft16(v, sign);
         const int o = (tid / Ns) * Ns * 16 + k;
 #pragma unroll
@@ -321,11 +341,13 @@ __device__ __forceinline__ int ilog2(int q)
 // ---------------------------------------------------------------------------
 template <class R, int MODE>
 __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__restrict__ in, typename cplx<R>::T *__restrict__ out,
-                                                const typename cplx<R>::T *__restrict__ corr, const typename cplx<R>::T *__restrict__ tw, Geom g)
+                                                const typename cplx<R>::T *__restrict__ corr, const double2 *__restrict__ tw, Geom g)
 {
     using C = typename cplx<R>::T;
     extern __shared__ char smem[];
     C *lds = reinterpret_cast<C *>(smem);
+    double2 *tt = reinterpret_cast<double2 *>(smem + (size_t)lpad(g.Q) * sizeof(C));   // two-level twiddle table
+    tw_stage(tt, tw, g.nf);
     const int line = blockIdx.x, tid = threadIdx.x, T = g.Q >> 4, L = ilog2(g.Q);
     const C *x = in + (size_t)line * g.Lpad;
     const int nx = line - g.R;
@@ -344,15 +366,15 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
                 const int m = g.P * (tid + r * T) + s;
                 v[r] = m < g.Lpad ? x[m] : C{0, 0};
             }
-            fft_line(lds, v, g.Q, L, +1, tw, g.P);
+            fft_line(lds, v, g.Q, L, +1, tt, g.P);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int kk = tid + i * T;
                 const C y = lds[lpad(kk)];
-                if (kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, tw[(kk * s) % g.nf]));
+                if (kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, tw_at<C>(tt, kk * s)));   // kk s < Q P
                 if (kk >= g.Q - g.R) {
                     const int n2 = kk - g.Q;
-                    acc_n[i] = cadd(acc_n[i], s == 0 ? y : cmul(y, tw[((n2 * s) % g.nf + g.nf) % g.nf]));
+                    acc_n[i] = cadd(acc_n[i], s == 0 ? y : cmul(y, tw_at<C>(tt, n2 * s + g.nf)));   // -nf < n2 s <= 0
                 }
             }
             __syncthreads();
@@ -374,9 +396,9 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
             for (int r = 0; r < 16; ++r) {
                 const int m = tid + r * T;
                 const C xm = m < g.Lpad ? x[m] : C{0, 0};
-                v[r] = s == 0 ? xm : cmul(xm, tw[(s * m) % g.nf]);
+                v[r] = s == 0 ? xm : cmul(xm, tw_at<C>(tt, s * m));   // m < Q
             }
-            fft_line(lds, v, g.Q, L, +1, tw, g.P);
+            fft_line(lds, v, g.Q, L, +1, tt, g.P);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int kp = tid + i * T;
@@ -401,11 +423,13 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
 template <class R, int MODE>
 __global__ __launch_bounds__(512) void k_fft_t2(const typename cplx<R>::T *__restrict__ in, void *__restrict__ outv, const int32_t *__restrict__ col_off,
                          const int32_t *__restrict__ col_ny0, const typename cplx<R>::T *__restrict__ corr,
-                         const typename cplx<R>::T *__restrict__ tw, Geom g)
+                         const double2 *__restrict__ tw, Geom g)
 {
     using C = typename cplx<R>::T;
     extern __shared__ char smem[];
     C *lds = reinterpret_cast<C *>(smem);
+    double2 *tt = reinterpret_cast<double2 *>(smem + (size_t)lpad(g.Q) * sizeof(C));   // two-level twiddle table
+    tw_stage(tt, tw, g.nf);
     const int line = blockIdx.x, tid = threadIdx.x, T = g.Q >> 4, L = ilog2(g.Q);
     int off = 0, cnt = 0, ny0 = 0;
     C cx{1, 0};
@@ -437,13 +461,13 @@ __global__ __launch_bounds__(512) void k_fft_t2(const typename cplx<R>::T *__res
             }
             v[r] = val;
         }
-        fft_line(lds, v, g.Q, L, -1, tw, g.P);
+        fft_line(lds, v, g.Q, L, -1, tt, g.P);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int m = tid + i * T;
             if (m < g.Lpad) {
                 C r2 = lds[lpad(m)];
-                if (s > 0) r2 = cmul(r2, cconj(tw[(s * m) % g.nf]));
+                if (s > 0) r2 = cmul(r2, cconj(tw_at<C>(tt, s * m)));   // m < Lpad <= Q
                 acc[i] = cadd(acc[i], r2);
             }
         }
@@ -1266,7 +1290,11 @@ hipError_t kernel_setup(Plan &)
     return hipFuncSetAttribute((const void *)k_local_fast<43>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-static size_t fft_lds_bytes(const Plan &p) { return (size_t)(p.g.Q + p.g.Q / 16) * 2 * p.sizeof_real; }
+static size_t fft_lds_bytes(const Plan &p)
+{
+    const size_t line = (size_t)(p.g.Q + p.g.Q / 16) * 2 * p.sizeof_real;   // multiple of 16 bytes
+    return line + (size_t)(64 + p.g.nf / 64) * sizeof(double2);
+}
 
 template <class R>
 static hipError_t fft_attrs(size_t bytes)
@@ -1298,7 +1326,7 @@ hipError_t launch_fft_rows1(Plan &p)
     const unsigned T = (unsigned)(g.Q / 16);
     if (p.precision == WFP2D_PREC_MIXED)
         hipLaunchKernelGGL((k_fft_t1<float, 0>), dim3(g.Lpad), dim3(T), sh, p.stream, (const float2 *)p.d_grid, (float2 *)p.d_T1,
-                           (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+                           (const float2 *)p.d_corr, (const double2 *)p.d_tw, g);
     else
         hipLaunchKernelGGL((k_fft_t1<double, 0>), dim3(g.Lpad), dim3(T), sh, p.stream, (const double2 *)p.d_grid, (double2 *)p.d_T1,
                            (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
@@ -1313,7 +1341,7 @@ hipError_t launch_fft_cols1(Plan &p)
     if (p.precision == WFP2D_PREC_MIXED) {
         transpose<float2>(p, p.d_T1, p.d_T1t, g.Lpad, g.N);
         hipLaunchKernelGGL((k_fft_t1<float, 1>), dim3(g.N), dim3(T), sh, p.stream, (const float2 *)p.d_T1t, (float2 *)p.d_F,
-                           (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+                           (const float2 *)p.d_corr, (const double2 *)p.d_tw, g);
     } else {
         transpose<double2>(p, p.d_T1, p.d_T1t, g.Lpad, g.N);
         hipLaunchKernelGGL((k_fft_t1<double, 1>), dim3(g.N), dim3(T), sh, p.stream, (const double2 *)p.d_T1t, (double2 *)p.d_F,
@@ -1368,7 +1396,7 @@ hipError_t launch_fft_cols2(Plan &p)
     const unsigned T = (unsigned)(g.Q / 16);
     if (p.precision == WFP2D_PREC_MIXED)
         hipLaunchKernelGGL((k_fft_t2<float, 0>), dim3(g.R + 1), dim3(T), sh, p.stream, (const float2 *)p.d_atot, p.d_T2, p.d_col_off,
-                           p.d_col_ny0, (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+                           p.d_col_ny0, (const float2 *)p.d_corr, (const double2 *)p.d_tw, g);
     else
         hipLaunchKernelGGL((k_fft_t2<double, 0>), dim3(g.R + 1), dim3(T), sh, p.stream, (const double2 *)p.d_atot, p.d_T2, p.d_col_off,
                            p.d_col_ny0, (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
@@ -1383,7 +1411,7 @@ hipError_t launch_fft_rows2(Plan &p)
     if (p.precision == WFP2D_PREC_MIXED) {
         transpose<float2>(p, p.d_T2, p.d_T2t, g.R + 1, g.Lpad);
         hipLaunchKernelGGL((k_fft_t2<float, 1>), dim3(g.Lpad), dim3(T), sh, p.stream, (const float2 *)p.d_T2t, p.d_cgrid, nullptr,
-                           nullptr, (const float2 *)p.d_corr, (const float2 *)p.d_tw, g);
+                           nullptr, (const float2 *)p.d_corr, (const double2 *)p.d_tw, g);
     } else {
         transpose<double2>(p, p.d_T2, p.d_T2t, g.R + 1, g.Lpad);
         hipLaunchKernelGGL((k_fft_t2<double, 1>), dim3(g.Lpad), dim3(T), sh, p.stream, (const double2 *)p.d_T2t, p.d_cgrid, nullptr,
