@@ -561,38 +561,36 @@ __global__ __launch_bounds__(256) void k_near(const ModeChunk *__restrict__ chun
     sincos(kap * g.dt, &s1, &c1);
     const double2 E = make_double2(c1, s1);
     const double inv = kap > 0.0 ? 1.0 / kap : 0.0;
+    double sL, cL;
+    sincos(kap * ((double)LA * g.dt), &sL, &cL);
     double2 D = Dst[pk], Cs = Cst[pk];
     double2 al = D;
-    double2 Pw = E;
+    double2 Pw = E;                                  // e^{i kappa j dt}
     double fs = 0.0, fc = 1.0;
     double2 Sin = make_double2(0.0, 0.0);
-    for (int l = 1; l < W; ++l) {
-        const double sk = kap > 0.0 ? Pw.y * inv : l * g.dt;
-        const int64_t slot = ((m - l) % W + W) % W;
-        const double2 S = to_d(cur[slot * H + pk]);
-        const double cf = sk * phi_in[l];
-        al.x += cf * S.x;
-        al.y += cf * S.y;
-        if (l == W - 1) {
+    // ring slots of S_{m-j} (near ring) and S_{m-LA-j} (lag ring), wrapped incrementally
+    const int b0 = (int)(((m % W) + W) % W), bL = (int)((((m - LA) % W) + W) % W);
+    int s_cur = b0, s_lag = bL;
+    // one rotation chain serves both edge FIRs:
+    // sin(kappa (LA + j) dt) = sin(kappa LA dt) cos(kappa j dt) + cos(kappa LA dt) sin(kappa j dt)
+    for (int j = 1; j < W; ++j) {
+        s_cur = s_cur == 0 ? W - 1 : s_cur - 1;
+        s_lag = s_lag == 0 ? W - 1 : s_lag - 1;
+        const double2 S = to_d(cur[(int64_t)s_cur * H + pk]);
+        const double2 T = to_d(lag[(int64_t)s_lag * H + pk]);
+        const double sk = kap > 0.0 ? Pw.y * inv : j * g.dt;
+        const double sLk = kap > 0.0 ? (sL * Pw.x + cL * Pw.y) * inv : (LA + j) * g.dt;
+        const double cf = sk * phi_in[j], cg = sLk * phi_in[W - j];
+        al.x += cf * S.x + cg * T.x;
+        al.y += cf * S.y + cg * T.y;
+        if (j == W - 1) {
             fs = sk;
             fc = Pw.x;
             Sin = S;
         }
         Pw = cmul(Pw, E);
     }
-    double sL, cL;
-    sincos(kap * ((double)LA * g.dt), &sL, &cL);
-    double2 Qw = cmul(make_double2(cL, sL), E);
-    for (int l = LA + 1; l < LA + W; ++l) {
-        const double sk = kap > 0.0 ? Qw.y * inv : l * g.dt;
-        const int64_t slot = ((m - l) % W + W) % W;
-        const double2 S = to_d(lag[slot * H + pk]);
-        const double cf = sk * phi_in[LA + W - l];
-        al.x += cf * S.x;
-        al.y += cf * S.y;
-        Qw = cmul(Qw, E);
-    }
-    const double2 SLA = to_d(lag[(((m - LA) % W + W) % W) * H + pk]);
+    const double2 SLA = to_d(lag[(int64_t)bL * H + pk]);
     const double scale = g.dt * (g.dk / (2.0 * M_PI)) * (g.dk / (2.0 * M_PI));
     atot[pk] = from_d<C>(make_double2(al.x * scale, al.y * scale));
     // advance the interior sums by one step
