@@ -72,6 +72,12 @@ typedef struct {
     int32_t device;   /* HIP device ordinal */
     void *stream;     /* hipStream_t for every launch (NULL = default stream) */
     int32_t spread_tile; /* type-1 spreading tile shape, 0 = default (3); see wfp2d_set_spread_tile */
+    /* Local part (Sec. 6, eq. local2): 0 (default) = store the list of source-target
+     * pairs with r < delta, with each pair's time-step panel and Chebyshev coordinate,
+     * once at init (12 bytes per pair) when it takes at most half of the free device
+     * memory, and stream it at every step; -1 = never (pairs are found at every step
+     * from the cell lists).  Both give the same sums up to the order of additions. */
+    int32_t local_pairs;
 } wfp2d_opts;
 
 typedef struct {
@@ -98,6 +104,8 @@ typedef struct {
     int32_t precision;
     int32_t n_regular_subpanels; /* local-weight sub-panels with r >= dt/2 */
     int32_t spread_tile;         /* current spreading tile shape code */
+    int32_t local_path;          /* local-part kernel: 0 generic, 1 per-step pair search, 2 stored pair lists */
+    int64_t local_pair_bytes;    /* device bytes of the stored pair lists (0 if none) */
 } wfp2d_info;
 
 /* Fill *opts with the defaults listed above.  Never fails for a valid pointer. */

@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("interp_order", ctypes.c_int32), ("lookahead", ctypes.c_int32),
                 ("Delta", ctypes.c_double), ("a", ctypes.c_double), ("Kf", ctypes.c_double),
                 ("b_Delta", ctypes.c_double), ("nufft_tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
-                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("spread_tile", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("spread_tile", ctypes.c_int32),
+                ("local_pairs", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -51,7 +52,8 @@ class Info(ctypes.Structure):
                 + [(n, ctypes.c_int64) for n in ("M", "Nx", "n_local_pairs", "sigma_depth", "bytes_device",
                                                  "steps_ingested", "step_reported")]
                 + [("precision", ctypes.c_int32), ("n_regular_subpanels", ctypes.c_int32),
-                   ("spread_tile", ctypes.c_int32)])
+                   ("spread_tile", ctypes.c_int32), ("local_path", ctypes.c_int32),
+                   ("local_pair_bytes", ctypes.c_int64)])
 
 
 _lib = None
@@ -152,7 +154,7 @@ class Wfp2d:
     def __init__(self, src_xy, tgt_xy, dt: float, W: int, tol: float = 1e-7, *, precision: str = "mixed",
                  interp_order: int = 20, lookahead: int = -1, Delta: float = 1.0, a: float = 0.0, Kf: float = 80.0,
                  b_Delta: float = 30.0, nufft_tol: float = 0.0, max_steps: int = 0, device: int = 0, stream=None,
-                 spread_tile: int = 0):
+                 spread_tile: int = 0, local_pairs: bool = True):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -170,6 +172,7 @@ class Wfp2d:
         o.interp_order, o.lookahead = int(interp_order), int(lookahead)
         o.Delta, o.a, o.Kf, o.b_Delta, o.nufft_tol = float(Delta), float(a), float(Kf), float(b_Delta), float(nufft_tol)
         o.max_steps, o.device, o.spread_tile = int(max_steps), int(device), int(spread_tile)
+        o.local_pairs = 0 if local_pairs else -1
         self.device = torch.device("cuda", int(device))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

@@ -41,6 +41,7 @@ T *Plan::alloc(int64_t count)
         fail(WFP2D_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
     allocs.push_back(ptr);
+    alloc_bytes.push_back(bytes);
     bytes_device += (int64_t)bytes;
     hip_check(hipMemset(ptr, 0, bytes), "hipMemset");
     return (T *)ptr;
@@ -52,7 +53,9 @@ void Plan::release(void *ptr)
     for (size_t i = 0; i < allocs.size(); ++i)
         if (allocs[i] == ptr) {
             (void)hipFree(ptr);
+            bytes_device -= (int64_t)alloc_bytes[i];
             allocs.erase(allocs.begin() + (std::ptrdiff_t)i);
+            alloc_bytes.erase(alloc_bytes.begin() + (std::ptrdiff_t)i);
             return;
         }
 }
@@ -179,6 +182,67 @@ static void build_spread_tiles(Plan &p, int code)
     p.sp_ty = ty;
     p.sp_ntx = ntx;
     p.sp_nty = nty;
+}
+
+// Pair lists of the local part (layout in k_pairs_build).  Built when the plan
+// can use the MFMA local kernels and the lists take at most half of the free
+// device memory; otherwise the local part finds its pairs at every step.
+// Segments: per cell with sources, ceil(sources / kFastSrc) chunks times
+// ceil(block targets / kPairTB) batches, numbered cell by cell.
+static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, const std::vector<int32_t> &tcell_start)
+{
+    const int n = p.ncell;
+    std::vector<int64_t> cseg((size_t)n * n + 1, 0);
+    for (int c = 0; c < n * n; ++c) {
+        const int64_t ns = cell_start[c + 1] - cell_start[c];
+        int64_t nseg = 0;
+        if (ns > 0) {
+            const int cx = c % n, cy = c / n, xa = std::max(0, cx - 2), xb = std::min(n - 1, cx + 2);
+            int64_t nt = 0;
+            for (int yy = std::max(0, cy - 2); yy <= std::min(n - 1, cy + 2); ++yy)
+                nt += tcell_start[(size_t)yy * n + xb + 1] - tcell_start[(size_t)yy * n + xa];
+            nseg = (ns + kFastSrc - 1) / kFastSrc * ((nt + kPairTB - 1) / kPairTB);
+        }
+        cseg[c + 1] = cseg[c] + nseg;
+    }
+    const int64_t nslot = cseg.back() * kFastSrc;
+    if (nslot == 0) return;
+    p.d_pair_cseg = p.alloc<int64_t>((int64_t)cseg.size());
+    upload(p.d_pair_cseg, cseg);
+    int64_t *d_cnt = p.alloc<int64_t>(nslot), *d_dcnt = p.alloc<int64_t>(nslot);
+    hip_check(launch_pairs_build(p, false, d_cnt, d_dcnt), "pair count");
+    hip_check(hipStreamSynchronize(p.stream), "pair count");
+    std::vector<int64_t> cnt(nslot), dcnt(nslot), off(nslot + 1, 0), doff(nslot + 1, 0);
+    hip_check(hipMemcpy(cnt.data(), d_cnt, nslot * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    hip_check(hipMemcpy(dcnt.data(), d_dcnt, nslot * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy D2H");
+    p.release(d_cnt);
+    p.release(d_dcnt);
+    for (int64_t s = 0; s < nslot; ++s) {
+        off[s + 1] = off[s] + cnt[s];
+        doff[s + 1] = doff[s] + dcnt[s];
+    }
+    const int64_t npair = off.back(), ndy = doff.back();
+    const int64_t bytes = (npair + ndy) * (int64_t)(sizeof(uint32_t) + sizeof(double)) + 2 * (nslot + 1) * (int64_t)sizeof(int64_t);
+    size_t free_b = 0, total_b = 0;
+    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    if ((double)bytes > 0.5 * (double)free_b) {
+        p.release(p.d_pair_cseg);
+        p.d_pair_cseg = nullptr;
+        return;
+    }
+    p.d_pair_off = p.alloc<int64_t>(nslot + 1);
+    p.d_pair_doff = p.alloc<int64_t>(nslot + 1);
+    upload(p.d_pair_off, off);
+    upload(p.d_pair_doff, doff);
+    p.d_pair_ent = p.alloc<uint32_t>(npair);
+    p.d_pair_x = p.alloc<double>(npair);
+    p.d_pair_dent = p.alloc<uint32_t>(ndy);
+    p.d_pair_dr = p.alloc<double>(ndy);
+    hip_check(launch_pairs_build(p, true, nullptr, nullptr), "pair fill");
+    hip_check(hipStreamSynchronize(p.stream), "pair fill");
+    p.local_pairs = true;
+    p.pair_bytes = bytes;
+    p.n_local_pairs = npair + ndy;
 }
 
 static void build(Plan &p, const double *src_xy, const double *tgt_xy)
@@ -395,23 +459,6 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     int64_t dmax = lev_min + LT.nlev - 1;
     g.sig_depth = std::max<int64_t>(p.LA, dmax) + p.lookahead + 1;
 
-    // local-pair count (reported; the local kernel finds pairs through the cell lists)
-    {
-        int64_t cnt = 0;
-        const double d2 = p.delta * p.delta;
-        for (int64_t i = 0; i < Nx; ++i) {
-            int c = tcell_sorted[i], cx = c % p.ncell, cy = c / p.ncell;
-            for (int yy = std::max(0, cy - 2); yy <= std::min(p.ncell - 1, cy + 2); ++yy)
-                for (int xx = std::max(0, cx - 2); xx <= std::min(p.ncell - 1, cx + 2); ++xx) {
-                    int cc = yy * p.ncell + xx;
-                    for (int32_t j = cell_start[cc]; j < cell_start[cc + 1]; ++j) {
-                        double dx = txy[i].x - sxy[j].x, dy = txy[i].y - sxy[j].y, r2 = dx * dx + dy * dy;
-                        if (r2 > 0.0 && r2 < d2) ++cnt;
-                    }
-                }
-        }
-        p.n_local_pairs = cnt;
-    }
 
     // NUFFT correction and twiddles
     std::vector<double> psihat;
@@ -520,6 +567,24 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_panel_base, LT.panel_base);
     p.d_panel_l2n = p.alloc<int32_t>(p.W);
     upload(p.d_panel_l2n, LT.panel_l2n);
+    if (p.local_fast && p.W <= 64 && p.opts.local_pairs == 0) build_pair_lists(p, cell_start, tcell_start);
+    // local-pair count (reported; without pair lists the local kernel finds pairs through the cell lists)
+    if (!p.local_pairs) {
+        int64_t cnt = 0;
+        const double d2 = p.delta * p.delta;
+        for (int64_t i = 0; i < Nx; ++i) {
+            int c = tcell_sorted[i], cx = c % p.ncell, cy = c / p.ncell;
+            for (int yy = std::max(0, cy - 2); yy <= std::min(p.ncell - 1, cy + 2); ++yy)
+                for (int xx = std::max(0, cx - 2); xx <= std::min(p.ncell - 1, cx + 2); ++xx) {
+                    int cc = yy * p.ncell + xx;
+                    for (int32_t j = cell_start[cc]; j < cell_start[cc + 1]; ++j) {
+                        double dx = txy[i].x - sxy[j].x, dy = txy[i].y - sxy[j].y, r2 = dx * dx + dy * dy;
+                        if (r2 > 0.0 && r2 < d2) ++cnt;
+                    }
+                }
+        }
+        p.n_local_pairs = cnt;
+    }
     p.state_bufs = {{p.d_step, sizeof(int64_t)},
                     {p.d_sig, (size_t)g.sig_depth * M * sizeof(double)},
                     {p.d_ring_cur, (size_t)p.W * p.n_modes * 2 * sr},
@@ -657,6 +722,7 @@ wfp2d_status wfp2d_default_opts(wfp2d_opts *o)
     o->device = 0;
     o->stream = nullptr;
     o->spread_tile = 0;
+    o->local_pairs = 0;
     return WFP2D_OK;
 }
 
@@ -677,6 +743,7 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
         if (o.precision != WFP2D_PREC_FP64 && o.precision != WFP2D_PREC_MIXED) fail(WFP2D_ERR_ARG, "unknown precision");
         if (o.interp_order < 2 || o.interp_order > 32) fail(WFP2D_ERR_ARG, "interp_order must be in [2, 32]");
         if (o.spread_tile < 0 || o.spread_tile > 5) fail(WFP2D_ERR_ARG, "spread_tile must be in [0, 5]");
+        if (o.local_pairs != 0 && o.local_pairs != -1) fail(WFP2D_ERR_ARG, "local_pairs must be 0 (auto) or -1 (never)");
         if (!(o.nufft_tol == 0.0 || (o.nufft_tol >= 1e-15 && o.nufft_tol < 1e-2)))
             fail(WFP2D_ERR_ARG, "nufft_tol must be 0 or in [1e-15, 1e-2) (kernel widths up to 16)");
         if (!(o.Delta > 0.0) || !(o.Kf > 0.0) || !(o.b_Delta > 0.0) || o.a < 0.0) fail(WFP2D_ERR_ARG, "bad Delta, Kf, b_Delta or a");
@@ -913,6 +980,8 @@ wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
     info->step_reported = p.steps - p.lookahead;
     info->precision = p.precision;
     info->spread_tile = p.spread_tile;
+    info->local_path = p.local_pairs ? 2 : p.local_fast ? 1 : 0;
+    info->local_pair_bytes = p.pair_bytes;
     info->n_regular_subpanels = p.n_reg;
     return WFP2D_OK;
 }

@@ -26,6 +26,7 @@ constexpr int kLocalQueue = 256;   //   queued pairs with r < dt/2 per chunk
 constexpr int kLocalOwn = 2;       //   targets owned per thread (regions up to 1024 targets in one pass)
 constexpr int kFastSrc = 16;       // fast local kernel: sources per chunk
 constexpr int kFastRow = 512;      //   max coefficient rows (regular sub-panels x Chebyshev terms)
+constexpr int kPairTB = 1024;      // pair-list local kernel: targets per batch (LDS sums)
 constexpr int kFastOwn = 4;        //   targets owned per thread
 
 // Work chunk of a per-mode kernel: modes [off, off+cnt) of packed column nx,
@@ -71,6 +72,7 @@ hipError_t launch_fft_cols2(Plan &p);
 hipError_t launch_fft_rows2(Plan &p);
 hipError_t launch_interp(Plan &p);
 hipError_t launch_local(Plan &p);
+hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt);
 hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n);
 hipError_t launch_combine_dot(Plan &p, const double *wts, double *acc);
 hipError_t launch_combine(Plan &p, double *u_out);
@@ -106,6 +108,7 @@ struct Plan {
 
     // ---- device memory ----
     std::vector<void *> allocs;
+    std::vector<size_t> alloc_bytes;  // size of each allocation in allocs
     int64_t bytes_device = 0;
     int64_t *d_step = nullptr;        // device-resident count of ingested steps
     double *d_sig = nullptr;          // [sig_depth][M] float64, sorted source order
@@ -161,6 +164,13 @@ struct Plan {
     int32_t *d_panel_base = nullptr;  // regular panel k -> first sub-panel, and log2 count
     int32_t *d_panel_l2n = nullptr;
     int32_t dy_base = 0, n_dy = 0;
+    // pair lists of the local part (built once when they fit; see k_pairs_build)
+    bool local_pairs = false;
+    int64_t pair_bytes = 0;
+    int64_t *d_pair_cseg = nullptr;   // first segment of each cell, [ncell^2 + 1]
+    int64_t *d_pair_off = nullptr, *d_pair_doff = nullptr;   // [n_seg * kFastSrc + 1]
+    uint32_t *d_pair_ent = nullptr, *d_pair_dent = nullptr;
+    double *d_pair_x = nullptr, *d_pair_dr = nullptr;
 
     std::string err;
 

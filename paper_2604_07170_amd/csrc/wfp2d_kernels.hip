@@ -1193,6 +1193,263 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
     }
 }
 
+// ---------------------------------------------------------------------------
+// Local part from pair lists made once per plan.  Sources and targets do not
+// move, so the set of pairs with 0 < r < delta, each pair's time-step panel k
+// and its Chebyshev coordinate x on that panel are the same at every step.
+// k_pairs_build finds them with the cell blocks of k_local_fast (a count pass,
+// then a fill pass at offsets scanned on the host) and stores them per segment
+// (a chunk of kFastSrc sources of one cell x a batch of kPairTB targets of the
+// cell's 5 x 5 block): for a pair with r >= dt/2 the word t | s << 16 | k << 20
+// (t: target in the batch, s: source in the chunk) and x in FP64; for a pair
+// with r < dt/2 (dyadic sub-panels) the word t | s << 16 and r.  Within a
+// segment the pairs are ordered by source, then by target.
+// k_local_pairs then does, per step and chunk: the profile coefficients
+// psi = C sigma with FP64 MFMA (as k_local_fast), then its waves take 128-pair
+// blocks of the segment in turn, two interleaved Clenshaw sums per lane, with
+// per-target sums in LDS; there is no candidate test, compaction or square
+// root per pair, and every wave gets the same number of pairs.
+// ---------------------------------------------------------------------------
+static_assert(kFastSrc <= 16 && kPairTB <= 65536, "pair words hold the source in 4 bits and the target in 16");
+
+struct PairLists {
+    const int64_t *cseg;          // first segment of each cell, [ncell^2 + 1]
+    const int64_t *off, *doff;    // first pair of each (segment, source in chunk), [n_seg * kFastSrc + 1]
+    const uint32_t *ent;          // regular pairs: t | s << 16 | k << 20
+    const double *x;              //   and their Chebyshev coordinates
+    const uint32_t *dent;         // pairs with r < dt/2: t | s << 16
+    const double *dr;             //   and their distances
+};
+
+struct PairBuild {
+    int64_t *cnt, *dcnt;          // count pass: pairs per (segment, source in chunk)
+    uint32_t *ent, *dent;         // fill pass: the lists, at the offsets of PairLists
+    double *x, *dr;
+    int fill;
+};
+
+// targets of the 5 x 5 block of `cell`: five runs of the sorted target order
+// (rows cy-2..cy+2); run r starts at rbeg[r] and holds block positions [rcum[r], rcum[r+1])
+__device__ __forceinline__ void cell_block_runs(const LocalArgs &A, int cell, int *rbeg, int *rcum)
+{
+    const int n = A.ncell, cx = cell % n, cy = cell / n;
+    const int xa = max(0, cx - 2), xb = min(n - 1, cx + 2);
+    int cum = 0, r = 0;
+    for (int yy = max(0, cy - 2); yy <= min(n - 1, cy + 2); ++yy, ++r) {
+        const int b = A.tcell_start[yy * n + xa], e = A.tcell_start[yy * n + xb + 1];
+        rbeg[r] = b;
+        rcum[r] = cum;
+        cum += e - b;
+    }
+    for (; r < 5; ++r) {
+        rbeg[r] = 0;
+        rcum[r] = cum;
+    }
+    rcum[5] = cum;
+}
+
+__device__ __forceinline__ int block_target(const int *rbeg, const int *rcum, int kk)
+{
+    int r = 0;
+    while (r < 4 && kk >= rcum[r + 1]) ++r;
+    return rbeg[r] + (kk - rcum[r]);
+}
+
+// One wave per (chunk, batch, source): the wave walks the batch's targets 64 at a
+// time and keeps the hits in target order (ballot + prefix count).
+__global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, PairBuild B, double dt, int W)
+{
+    __shared__ int rbeg[5], rcum[6];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int n = A.ncell;
+    const double d2 = A.delta * A.delta, q2 = 0.25 * dt * dt;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int cell = blockIdx.x; cell < n * n; cell += gridDim.x) {
+        const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
+        const int64_t seg0 = P.cseg[cell];
+        if (s0 == s1 || P.cseg[cell + 1] == seg0) continue;     // uniform across the workgroup
+        __syncthreads();                                         // the previous cell's runs are no longer read
+        if (tid == 0) cell_block_runs(A, cell, rbeg, rcum);
+        __syncthreads();
+        const int NT = rcum[5], nb = (NT + kPairTB - 1) / kPairTB;
+        const int nch = (s1 - s0 + kFastSrc - 1) / kFastSrc;
+        for (int task = wave; task < nch * nb * kFastSrc; task += nwave) {
+            const int sl = task % kFastSrc, ib = task / kFastSrc, b = ib % nb, i = ib / nb;
+            const int64_t slot = (seg0 + (int64_t)i * nb + b) * kFastSrc + sl;
+            const int j = s0 + i * kFastSrc + sl;
+            int64_t c_reg = 0, c_dy = 0;
+            if (j < s1) {
+                const double2 y = A.sxy[j];
+                const int tb0 = b * kPairTB, ntb = min(kPairTB, NT - tb0);
+                const int64_t o_reg = B.fill ? P.off[slot] : 0, o_dy = B.fill ? P.doff[slot] : 0;
+                for (int t0 = 0; t0 < ntb; t0 += 64) {
+                    const int t = t0 + lane;
+                    bool reg = false, dya = false;
+                    double r2 = 0.0;
+                    if (t < ntb) {
+                        const double2 xt = A.txy[block_target(rbeg, rcum, tb0 + t)];
+                        const double dx = xt.x - y.x, dy = xt.y - y.y;
+                        r2 = dx * dx + dy * dy;
+                        const bool hit = r2 > 0.0 && r2 < d2;
+                        dya = hit && r2 < q2;
+                        reg = hit && !dya;
+                    }
+                    const uint64_t mr = __ballot(reg), md = __ballot(dya);
+                    if (B.fill && reg) {
+                        const int64_t e = o_reg + c_reg + __popcll(mr & below);
+                        double x;
+                        const int k = fast_panel(A, sqrt(r2), W, dt, x);
+                        B.ent[e] = (uint32_t)t | ((uint32_t)sl << 16) | ((uint32_t)k << 20);
+                        B.x[e] = x;
+                    }
+                    if (B.fill && dya) {
+                        const int64_t e = o_dy + c_dy + __popcll(md & below);
+                        B.dent[e] = (uint32_t)t | ((uint32_t)sl << 16);
+                        B.dr[e] = sqrt(r2);
+                    }
+                    c_reg += __popcll(mr);
+                    c_dy += __popcll(md);
+                }
+            }
+            if (!B.fill && lane == 0) {
+                B.cnt[slot] = c_reg;
+                B.dcnt[slot] = c_dy;
+            }
+        }
+    }
+}
+
+template <int NL>
+__global__ __launch_bounds__(kFastRow) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
+{
+    const int64_t m = step[0] - g.lookahead;
+    extern __shared__ double fast_lds[];              // psi [kFastSrc][psiSrc]
+    __shared__ double sigs[kFastSrc * NL];
+    __shared__ double tacc[kPairTB];
+    __shared__ int rbeg[5], rcum[6];
+
+    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = bd >> 6;
+    const int n = A.ncell, D = kChebDeg, nrow = A.n_reg * kChebDeg, psiSrc = psi_src_stride(A.n_reg);
+    double *psi = fast_lds;
+    constexpr int KS = (NL + 3) / 4;
+    const int nblk = (nrow + 15) / 16;
+
+    for (int cell = blockIdx.x; cell < n * n; cell += gridDim.x) {
+        const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
+        const int64_t seg0 = P.cseg[cell];
+        if (s0 == s1 || P.cseg[cell + 1] == seg0) continue;     // no sources, or no targets in the block
+        if (tid == 0) cell_block_runs(A, cell, rbeg, rcum);
+        __syncthreads();
+        const int NT = rcum[5], nb = (NT + kPairTB - 1) / kPairTB;
+        const int nch = (s1 - s0 + kFastSrc - 1) / kFastSrc;
+        if (nb == 1)                                   // one batch: the sums stay in LDS for the whole cell
+            for (int t = tid; t < NT; t += bd) tacc[t] = 0.0;
+        for (int i = 0; i < nch; ++i) {
+            const int sb = s0 + i * kFastSrc, ns = min(kFastSrc, s1 - sb);
+            for (int e = tid; e < ns * NL; e += bd) {
+                const int sidx = e / NL, d = e - sidx * NL;
+                sigs[e] = A.sig[sig_slot(m, d, g) * g.M + sb + sidx];
+            }
+            {
+                // psi = C sigma: the same FP64 MFMA tiling as k_local_fast
+                double ca[kFastRB][KS];
+#pragma unroll
+                for (int j = 0; j < kFastRB; ++j) {
+                    const int row = (wave + j * nwave) * 16 + (lane & 15);
+                    const double *__restrict__ crow = A.creg + (size_t)min(row, nrow - 1) * NL;
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int d = 4 * ks + (lane >> 4);
+                        ca[j][ks] = (row < nrow && d < NL) ? crow[d] : 0.0;
+                    }
+                }
+                __syncthreads();
+                mfma_d4 acc[kFastRB];
+#pragma unroll
+                for (int j = 0; j < kFastRB; ++j) acc[j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+                const int q = lane & 15;
+#pragma unroll
+                for (int j = 0; j < kFastRB; ++j) {
+                    const int rb = wave + j * nwave;
+                    if (rb >= nblk) continue;              // uniform across the wave
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int d = 4 * ks + (lane >> 4);
+                        const double b = (q < ns && d < NL) ? sigs[q * NL + d] : 0.0;
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[j][ks], b, acc[j], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kFastRB; ++j) {
+                    const int rb = wave + j * nwave;
+                    if (rb >= nblk || q >= ns) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rb * 16 + (lane >> 4) + 4 * r;
+                        if (row < nrow) psi[q * psiSrc + (row / D) * kPsiRow + row % D] = acc[j][r];
+                    }
+                }
+            }
+            __syncthreads();
+            for (int b = 0; b < nb; ++b) {
+                const int tb0 = b * kPairTB, ntb = min(kPairTB, NT - tb0);
+                if (nb > 1) {
+                    for (int t = tid; t < ntb; t += bd) tacc[t] = 0.0;
+                    __syncthreads();
+                }
+                const int64_t seg = seg0 + (int64_t)i * nb + b;
+                const int64_t p0 = P.off[seg * kFastSrc], p1 = P.off[(seg + 1) * kFastSrc];
+                const int64_t stride = (int64_t)nwave * 128;
+                int64_t base = p0 + (int64_t)wave * 128;
+                // the next block's words and coordinates are loaded while this block is evaluated
+                uint32_t nw0 = 0u, nw1 = 0u;
+                double nx0 = 0.0, nx1 = 0.0;
+                auto fetch = [&](int64_t bs) {
+                    const int64_t e0 = bs + lane, e1 = e0 + 64;
+                    nw0 = e0 < p1 ? P.ent[e0] : 0u;
+                    nx0 = e0 < p1 ? P.x[e0] : 0.0;
+                    nw1 = e1 < p1 ? P.ent[e1] : 0u;
+                    nx1 = e1 < p1 ? P.x[e1] : 0.0;
+                };
+                if (base < p1) fetch(base);
+                for (; base < p1; base += stride) {
+                    const uint32_t w0 = nw0, w1 = nw1;
+                    const double x0 = nx0, x1 = nx1;
+                    const bool v0 = base + lane < p1, v1 = base + 64 + lane < p1;
+                    if (base + stride < p1) fetch(base + stride);
+                    double u0, u1;
+                    cheb_eval2(psi + (int)((w0 >> 16) & 15u) * psiSrc + (int)(w0 >> 20) * kPsiRow, x0,
+                               psi + (int)((w1 >> 16) & 15u) * psiSrc + (int)(w1 >> 20) * kPsiRow, x1, u0, u1);
+                    if (v0) atomicAdd(&tacc[w0 & 0xffffu], u0);
+                    if (v1) atomicAdd(&tacc[w1 & 0xffffu], u1);
+                }
+                // pairs with r < dt/2: one wavefront per pair, lanes over levels
+                const int64_t q0 = P.doff[seg * kFastSrc], q1 = P.doff[(seg + 1) * kFastSrc];
+                for (int64_t q = q0 + wave; q < q1; q += nwave) {
+                    const uint32_t wq = P.dent[q];
+                    const double r = P.dr[q];
+                    const int sidx = (int)((wq >> 16) & 15u);
+                    const int sub = dyadic_sub(A, r * A.inv_dt);
+                    const double xc = sub_coord(A.subs[sub], r);
+                    double v = 0.0;
+                    for (int d = lane; d < NL; d += 64)
+                        v = fma(cheb_eval(A.cheb + ((size_t)sub * NL + d) * D, xc), sigs[sidx * NL + d], v);
+                    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                    if (lane == 0) atomicAdd(&tacc[wq & 0xffffu], v);
+                }
+                __syncthreads();
+                if (nb > 1 || i == nch - 1) {
+                    for (int t = tid; t < ntb; t += bd) {
+                        const double v = tacc[t];
+                        if (v != 0.0) unsafeAtomicAdd(&A.ul[block_target(rbeg, rcum, tb0 + t)], v);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    }
+}
+
 // Grid-stride fill: a dispatch covers at most 2^32 work-items, and the sigma
 // ring alone can exceed that (4.3e9 doubles at 10^6 sources).
 __global__ void k_zero_f64(double *__restrict__ p, int64_t n)
@@ -1283,9 +1540,12 @@ hipError_t kernel_setup(Plan &)
 {
     const int bytes = kFastSrc * (kFastRow / kChebDeg * (kChebDeg + 1) + 1) * (int)sizeof(double) +
                       (kFastRow / 64) * kFastRing * 12;
-    hipError_t e = hipFuncSetAttribute((const void *)k_local_fast<35>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_local_fast<43>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const int pbytes = kFastSrc * (kFastRow / kChebDeg * (kChebDeg + 1) + 1) * (int)sizeof(double);
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_local_fast<35>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_local_fast<43>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_local_pairs<35>, hipFuncAttributeMaxDynamicSharedMemorySize, pbytes))) return e;
+    return hipFuncSetAttribute((const void *)k_local_pairs<43>, hipFuncAttributeMaxDynamicSharedMemorySize, pbytes);
 }
 
 static size_t fft_lds_bytes(const Plan &p)
@@ -1431,7 +1691,7 @@ hipError_t launch_interp(Plan &p)
     return hipGetLastError();
 }
 
-hipError_t launch_local(Plan &p)
+static LocalArgs local_args(const Plan &p)
 {
     LocalArgs A;
     A.txy = p.d_tgt_xy;
@@ -1454,6 +1714,54 @@ hipError_t launch_local(Plan &p)
     A.inv_dt = 1.0 / p.dt;
     A.two_over_ua = 2.0 / sqrt(p.dt);
     A.two_over_ua0 = 2.0 / sqrt(0.5 * p.dt);
+    return A;
+}
+
+static PairLists pair_lists(const Plan &p)
+{
+    PairLists P;
+    P.cseg = p.d_pair_cseg;
+    P.off = p.d_pair_off;
+    P.doff = p.d_pair_doff;
+    P.ent = p.d_pair_ent;
+    P.x = p.d_pair_x;
+    P.dent = p.d_pair_dent;
+    P.dr = p.d_pair_dr;
+    return P;
+}
+
+hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt)
+{
+    const LocalArgs A = local_args(p);
+    PairLists P = pair_lists(p);
+    PairBuild B;
+    B.cnt = cnt;
+    B.dcnt = dcnt;
+    B.ent = p.d_pair_ent;
+    B.x = p.d_pair_x;
+    B.dent = p.d_pair_dent;
+    B.dr = p.d_pair_dr;
+    B.fill = fill ? 1 : 0;
+    const unsigned grid = (unsigned)std::min(p.ncell * p.ncell, 4096);
+    hipLaunchKernelGGL(k_pairs_build, dim3(grid), dim3(256), 0, p.stream, A, P, B, p.dt, (int)p.W);
+    return hipGetLastError();
+}
+
+hipError_t launch_local(Plan &p)
+{
+    const LocalArgs A = local_args(p);
+    if (p.local_pairs) {
+        const int nrow = p.n_reg * kChebDeg;
+        const unsigned threads = (unsigned)((nrow + 63) / 64 * 64);
+        const unsigned grid = (unsigned)std::min(p.ncell * p.ncell, 2 * 256);
+        const size_t lds = (size_t)kFastSrc * (p.n_reg * (kChebDeg + 1) + 1) * sizeof(double);
+        const PairLists P = pair_lists(p);
+        if (p.g.nlev == 35)
+            hipLaunchKernelGGL(k_local_pairs<35>, dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g);
+        else
+            hipLaunchKernelGGL(k_local_pairs<43>, dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g);
+        return hipGetLastError();
+    }
     if (p.local_fast) {
         const int nrow = p.n_reg * kChebDeg;
         const unsigned threads = (unsigned)((nrow + 63) / 64 * 64);

@@ -75,3 +75,29 @@ def test_adjoint_and_state_entry_points_reject_without_a_device():
     assert lib.wfp2d_save_state(None, None, 0) == -6
     assert lib.wfp2d_load_state(None, None, 0) == -6
     assert lib.wfp2d_reset(None) == -6
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of wfp2d_opts and wfp2d_info have the header's field offsets
+    and sizes (a C program built against include/wfp2d.h prints them)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "wfp2d.h"', "int main(void) {"]
+    for cname, cls in (("wfp2d_opts", pa.Opts), ("wfp2d_info", pa.Info)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.dirname(pa.HEADER_PATH), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in (("wfp2d_opts", pa.Opts), ("wfp2d_info", pa.Info)):
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
