@@ -187,28 +187,41 @@ static void build_spread_tiles(Plan &p, int code)
 // Pair lists of the local part (layout in k_pairs_build).  Built when the plan
 // can use the MFMA local kernels and the lists take at most half of the free
 // device memory; otherwise the local part finds its pairs at every step.
-// Segments: per cell with sources, ceil(sources / kFastSrc) chunks times
-// ceil(block targets / kPairTB) batches, numbered cell by cell.
+// Segments: per work cell (sources, and targets in its 5 x 5 block),
+// ceil(sources / kFastSrc) chunks times ceil(block targets / kPairTB) batches,
+// numbered cell by cell.
 static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, const std::vector<int32_t> &tcell_start)
 {
     const int n = p.ncell;
-    std::vector<int64_t> cseg((size_t)n * n + 1, 0);
+    std::vector<int32_t> wrec;
+    std::vector<int64_t> wseg(1, 0);
     for (int c = 0; c < n * n; ++c) {
-        const int64_t ns = cell_start[c + 1] - cell_start[c];
-        int64_t nseg = 0;
-        if (ns > 0) {
-            const int cx = c % n, cy = c / n, xa = std::max(0, cx - 2), xb = std::min(n - 1, cx + 2);
-            int64_t nt = 0;
-            for (int yy = std::max(0, cy - 2); yy <= std::min(n - 1, cy + 2); ++yy)
-                nt += tcell_start[(size_t)yy * n + xb + 1] - tcell_start[(size_t)yy * n + xa];
-            nseg = (ns + kFastSrc - 1) / kFastSrc * ((nt + kPairTB - 1) / kPairTB);
+        const int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+        if (s1 == s0) continue;
+        const int cx = c % n, cy = c / n, xa = std::max(0, cx - 2), xb = std::min(n - 1, cx + 2);
+        int32_t rec[kPairRec] = {s0, s1};
+        int32_t cum = 0;
+        int r = 0;
+        for (int yy = std::max(0, cy - 2); yy <= std::min(n - 1, cy + 2); ++yy, ++r) {
+            const int32_t b = tcell_start[(size_t)yy * n + xa], e = tcell_start[(size_t)yy * n + xb + 1];
+            rec[2 + r] = b;
+            rec[7 + r] = cum;
+            cum += e - b;
         }
-        cseg[c + 1] = cseg[c] + nseg;
+        for (; r < 5; ++r) rec[7 + r] = cum;
+        rec[12] = cum;
+        if (cum == 0) continue;
+        const int64_t nseg = (int64_t)(s1 - s0 + kFastSrc - 1) / kFastSrc * ((cum + kPairTB - 1) / kPairTB);
+        wrec.insert(wrec.end(), rec, rec + kPairRec);
+        wseg.push_back(wseg.back() + nseg);
     }
-    const int64_t nslot = cseg.back() * kFastSrc;
-    if (nslot == 0) return;
-    p.d_pair_cseg = p.alloc<int64_t>((int64_t)cseg.size());
-    upload(p.d_pair_cseg, cseg);
+    p.pair_n_work = (int64_t)wseg.size() - 1;
+    const int64_t nslot = wseg.back() * kFastSrc;
+    if (nslot == 0 || p.pair_n_work > INT32_MAX) return;
+    p.d_pair_wrec = p.alloc<int32_t>((int64_t)wrec.size());
+    upload(p.d_pair_wrec, wrec);
+    p.d_pair_wseg = p.alloc<int64_t>((int64_t)wseg.size());
+    upload(p.d_pair_wseg, wseg);
     int64_t *d_cnt = p.alloc<int64_t>(nslot), *d_dcnt = p.alloc<int64_t>(nslot);
     hip_check(launch_pairs_build(p, false, d_cnt, d_dcnt), "pair count");
     hip_check(hipStreamSynchronize(p.stream), "pair count");
@@ -222,18 +235,34 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
         doff[s + 1] = doff[s] + dcnt[s];
     }
     const int64_t npair = off.back(), ndy = doff.back();
-    const int64_t bytes = (npair + ndy) * (int64_t)(sizeof(uint32_t) + sizeof(double)) + 2 * (nslot + 1) * (int64_t)sizeof(int64_t);
+    const int64_t bytes = (npair + ndy) * (int64_t)(sizeof(uint32_t) + sizeof(double)) +
+                          2 * (nslot + 1 + nslot / kFastSrc + 1) * (int64_t)sizeof(int64_t);
     size_t free_b = 0, total_b = 0;
     hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     if ((double)bytes > 0.5 * (double)free_b) {
-        p.release(p.d_pair_cseg);
-        p.d_pair_cseg = nullptr;
+        p.release(p.d_pair_wrec);
+        p.release(p.d_pair_wseg);
+        p.d_pair_wrec = nullptr;
+        p.d_pair_wseg = nullptr;
         return;
     }
     p.d_pair_off = p.alloc<int64_t>(nslot + 1);
     p.d_pair_doff = p.alloc<int64_t>(nslot + 1);
     upload(p.d_pair_off, off);
     upload(p.d_pair_doff, doff);
+    {
+        // the same offsets per segment (every kFastSrc-th), read by the per-step kernel
+        const int64_t nseg = nslot / kFastSrc;
+        std::vector<int64_t> so(nseg + 1), sdo(nseg + 1);
+        for (int64_t s = 0; s <= nseg; ++s) {
+            so[s] = off[s * kFastSrc];
+            sdo[s] = doff[s * kFastSrc];
+        }
+        p.d_seg_off = p.alloc<int64_t>(nseg + 1);
+        p.d_seg_doff = p.alloc<int64_t>(nseg + 1);
+        upload(p.d_seg_off, so);
+        upload(p.d_seg_doff, sdo);
+    }
     p.d_pair_ent = p.alloc<uint32_t>(npair);
     p.d_pair_x = p.alloc<double>(npair);
     p.d_pair_dent = p.alloc<uint32_t>(ndy);
@@ -248,6 +277,11 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
 static void build(Plan &p, const double *src_xy, const double *tgt_xy)
 {
     hip_check(hipSetDevice(p.device), "hipSetDevice");
+    {
+        int ncu = 0;
+        hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device), "hipDeviceGetAttribute");
+        p.n_cu = std::max(1, ncu);
+    }
     const int64_t M = p.M, Nx = p.Nx;
     p.sizeof_real = (p.precision == WFP2D_PREC_MIXED) ? 4 : 8;
 
@@ -567,7 +601,8 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_panel_base, LT.panel_base);
     p.d_panel_l2n = p.alloc<int32_t>(p.W);
     upload(p.d_panel_l2n, LT.panel_l2n);
-    if (p.local_fast && p.W <= 64 && p.opts.local_pairs == 0) build_pair_lists(p, cell_start, tcell_start);
+    if (p.local_fast && p.W <= 64 && p.n_reg * kChebDeg <= kPairThreads / 64 * kPairRB * 16 && p.opts.local_pairs == 0)
+        build_pair_lists(p, cell_start, tcell_start);
     // local-pair count (reported; without pair lists the local kernel finds pairs through the cell lists)
     if (!p.local_pairs) {
         int64_t cnt = 0;

@@ -27,6 +27,9 @@ constexpr int kLocalOwn = 2;       //   targets owned per thread (regions up to 
 constexpr int kFastSrc = 16;       // fast local kernel: sources per chunk
 constexpr int kFastRow = 512;      //   max coefficient rows (regular sub-panels x Chebyshev terms)
 constexpr int kPairTB = 1024;      // pair-list local kernel: targets per batch (LDS sums)
+constexpr int kPairRec = 16;       //   int32 per work-cell record
+constexpr int kPairThreads = 1024; //   threads per workgroup (16 waves, one workgroup per CU)
+constexpr int kPairRB = 2;         //   16-row blocks of the coefficient table per wave
 constexpr int kFastOwn = 4;        //   targets owned per thread
 
 // Work chunk of a per-mode kernel: modes [off, off+cnt) of packed column nx,
@@ -167,8 +170,12 @@ struct Plan {
     // pair lists of the local part (built once when they fit; see k_pairs_build)
     bool local_pairs = false;
     int64_t pair_bytes = 0;
-    int64_t *d_pair_cseg = nullptr;   // first segment of each cell, [ncell^2 + 1]
+    int64_t pair_n_work = 0;          // cells with sources and with targets in their 5 x 5 block
+    int32_t *d_pair_wrec = nullptr;   // their records: s0, s1, rbeg[5], rcum[6], padding (16 int32)
+    int64_t *d_pair_wseg = nullptr;   // first segment of each work cell, [n_work + 1]
     int64_t *d_pair_off = nullptr, *d_pair_doff = nullptr;   // [n_seg * kFastSrc + 1]
+    int64_t *d_seg_off = nullptr, *d_seg_doff = nullptr;     // first pair of each segment, [n_seg + 1]
+    int32_t n_cu = 256;               // compute units of the device (persistent grids)
     uint32_t *d_pair_ent = nullptr, *d_pair_dent = nullptr;
     double *d_pair_x = nullptr, *d_pair_dr = nullptr;
 

@@ -1212,9 +1212,17 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
 // ---------------------------------------------------------------------------
 static_assert(kFastSrc <= 16 && kPairTB <= 65536, "pair words hold the source in 4 bits and the target in 16");
 
+// Work cells (cells with sources and with targets in their block), one record
+// of kCellRec int32 each: the cell's sources [s0, s1) in sorted order, then the
+// five runs of its 5 x 5 target block (rbeg[5], rcum[6]; see cell_block_runs).
+constexpr int kCellRec = kPairRec;
+
 struct PairLists {
-    const int64_t *cseg;          // first segment of each cell, [ncell^2 + 1]
+    const int32_t *wrec;          // [n_work][kCellRec]
+    const int64_t *wseg;          // first segment of each work cell, [n_work + 1]
+    int n_work;
     const int64_t *off, *doff;    // first pair of each (segment, source in chunk), [n_seg * kFastSrc + 1]
+    const int64_t *soff, *sdoff;  // first pair of each segment, [n_seg + 1]
     const uint32_t *ent;          // regular pairs: t | s << 16 | k << 20
     const double *x;              //   and their Chebyshev coordinates
     const uint32_t *dent;         // pairs with r < dt/2: t | s << 16
@@ -1228,26 +1236,8 @@ struct PairBuild {
     int fill;
 };
 
-// targets of the 5 x 5 block of `cell`: five runs of the sorted target order
-// (rows cy-2..cy+2); run r starts at rbeg[r] and holds block positions [rcum[r], rcum[r+1])
-__device__ __forceinline__ void cell_block_runs(const LocalArgs &A, int cell, int *rbeg, int *rcum)
-{
-    const int n = A.ncell, cx = cell % n, cy = cell / n;
-    const int xa = max(0, cx - 2), xb = min(n - 1, cx + 2);
-    int cum = 0, r = 0;
-    for (int yy = max(0, cy - 2); yy <= min(n - 1, cy + 2); ++yy, ++r) {
-        const int b = A.tcell_start[yy * n + xa], e = A.tcell_start[yy * n + xb + 1];
-        rbeg[r] = b;
-        rcum[r] = cum;
-        cum += e - b;
-    }
-    for (; r < 5; ++r) {
-        rbeg[r] = 0;
-        rcum[r] = cum;
-    }
-    rcum[5] = cum;
-}
-
+// targets of a cell's 5 x 5 block: five runs of the sorted target order (rows
+// cy-2..cy+2); run r starts at rbeg[r] and holds block positions [rcum[r], rcum[r+1])
 __device__ __forceinline__ int block_target(const int *rbeg, const int *rcum, int kk)
 {
     int r = 0;
@@ -1259,18 +1249,17 @@ __device__ __forceinline__ int block_target(const int *rbeg, const int *rcum, in
 // time and keeps the hits in target order (ballot + prefix count).
 __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, PairBuild B, double dt, int W)
 {
-    __shared__ int rbeg[5], rcum[6];
+    __shared__ int rec[kCellRec];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    const int n = A.ncell;
     const double d2 = A.delta * A.delta, q2 = 0.25 * dt * dt;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (int cell = blockIdx.x; cell < n * n; cell += gridDim.x) {
-        const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
-        const int64_t seg0 = P.cseg[cell];
-        if (s0 == s1 || P.cseg[cell + 1] == seg0) continue;     // uniform across the workgroup
-        __syncthreads();                                         // the previous cell's runs are no longer read
-        if (tid == 0) cell_block_runs(A, cell, rbeg, rcum);
+    const int *rbeg = rec + 2, *rcum = rec + 7;
+    for (int wk = blockIdx.x; wk < P.n_work; wk += gridDim.x) {
+        __syncthreads();                                         // the previous record is no longer read
+        if (tid < kCellRec) rec[tid] = P.wrec[(int64_t)wk * kCellRec + tid];
         __syncthreads();
+        const int s0 = rec[0], s1 = rec[1];
+        const int64_t seg0 = P.wseg[wk];
         const int NT = rcum[5], nb = (NT + kPairTB - 1) / kPairTB;
         const int nch = (s1 - s0 + kFastSrc - 1) / kFastSrc;
         for (int task = wave; task < nch * nb * kFastSrc; task += nwave) {
@@ -1319,57 +1308,93 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
     }
 }
 
+// a value the whole wave holds (loaded from LDS or memory), moved to a scalar register
+// so that loops and branches on it are uniform
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <int NL>
-__global__ __launch_bounds__(kFastRow) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
+__global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
 {
     const int64_t m = step[0] - g.lookahead;
     extern __shared__ double fast_lds[];              // psi [kFastSrc][psiSrc]
     __shared__ double sigs[kFastSrc * NL];
     __shared__ double tacc[kPairTB];
-    __shared__ int rbeg[5], rcum[6];
+    __shared__ int64_t slot_base[NL];                 // ring offset of sigma level d at this step
+    __shared__ int rec[kCellRec];
 
-    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = bd >> 6;
-    const int n = A.ncell, D = kChebDeg, nrow = A.n_reg * kChebDeg, psiSrc = psi_src_stride(A.n_reg);
+    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wave = uniform(tid >> 6), nwave = bd >> 6;
+    const int D = kChebDeg, nrow = A.n_reg * kChebDeg, psiSrc = psi_src_stride(A.n_reg);
     double *psi = fast_lds;
     constexpr int KS = (NL + 3) / 4;
     const int nblk = (nrow + 15) / 16;
+    const int *rbeg = rec + 2, *rcum = rec + 7;
+    // the record of this workgroup's next work cell is loaded one cell ahead
+    int nrec = (tid < kCellRec && (int)blockIdx.x < P.n_work) ? P.wrec[(int64_t)blockIdx.x * kCellRec + tid] : 0;
+    if (tid < NL) slot_base[tid] = sig_slot(m, tid, g) * g.M;
+    // A operands of this wave's row blocks of C (FP64 MFMA 16x16x4: lane holds
+    // C[rb*16 + lane%16][4 ks + lane/16]), loaded once and kept in registers
+    double ca[kPairRB][KS];
+#pragma unroll
+    for (int j = 0; j < kPairRB; ++j) {
+        const int row = (wave + j * nwave) * 16 + (lane & 15);
+        const double *__restrict__ crow = A.creg + (size_t)min(row, nrow - 1) * NL;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int d = 4 * ks + (lane >> 4);
+            ca[j][ks] = (row < nrow && d < NL) ? crow[d] : 0.0;
+        }
+    }
 
-    for (int cell = blockIdx.x; cell < n * n; cell += gridDim.x) {
-        const int s0 = A.scell_start[cell], s1 = A.scell_start[cell + 1];
-        const int64_t seg0 = P.cseg[cell];
-        if (s0 == s1 || P.cseg[cell + 1] == seg0) continue;     // no sources, or no targets in the block
-        if (tid == 0) cell_block_runs(A, cell, rbeg, rcum);
+    // pair words and coordinates of a wave's next 128-pair block (loaded ahead of use)
+    uint32_t nw0 = 0u, nw1 = 0u;
+    double nx0 = 0.0, nx1 = 0.0;
+    auto fetch = [&](int64_t bs, int64_t pend) {
+        const int64_t e0 = bs + lane, e1 = e0 + 64;
+        nw0 = e0 < pend ? P.ent[e0] : 0u;
+        nx0 = e0 < pend ? P.x[e0] : 0.0;
+        nw1 = e1 < pend ? P.ent[e1] : 0u;
+        nx1 = e1 < pend ? P.x[e1] : 0.0;
+    };
+
+    for (int wk = blockIdx.x; wk < P.n_work; wk += gridDim.x) {
+        if (tid < kCellRec) {
+            rec[tid] = nrec;
+            const int nk = wk + (int)gridDim.x;
+            nrec = nk < P.n_work ? P.wrec[(int64_t)nk * kCellRec + tid] : 0;
+        }
         __syncthreads();
-        const int NT = rcum[5], nb = (NT + kPairTB - 1) / kPairTB;
+        const int s0 = uniform(rec[0]), s1 = uniform(rec[1]);
+        const int64_t seg0 = uniform64(P.wseg[wk]);
+        const int NT = uniform(rcum[5]), nb = (NT + kPairTB - 1) / kPairTB;
         const int nch = (s1 - s0 + kFastSrc - 1) / kFastSrc;
         if (nb == 1)                                   // one batch: the sums stay in LDS for the whole cell
             for (int t = tid; t < NT; t += bd) tacc[t] = 0.0;
         for (int i = 0; i < nch; ++i) {
             const int sb = s0 + i * kFastSrc, ns = min(kFastSrc, s1 - sb);
+            // segment bounds of batch 0, loaded before sigma (loads complete in order)
+            const int64_t seg_i = seg0 + (int64_t)i * nb;
+            const int64_t p0 = uniform64(P.soff[seg_i]), p1 = uniform64(P.soff[seg_i + 1]);
+            const int64_t q0 = uniform64(P.sdoff[seg_i]), q1 = uniform64(P.sdoff[seg_i + 1]);
             for (int e = tid; e < ns * NL; e += bd) {
                 const int sidx = e / NL, d = e - sidx * NL;
-                sigs[e] = A.sig[sig_slot(m, d, g) * g.M + sb + sidx];
+                sigs[e] = A.sig[slot_base[d] + sb + sidx];
             }
             {
                 // psi = C sigma: the same FP64 MFMA tiling as k_local_fast
-                double ca[kFastRB][KS];
-#pragma unroll
-                for (int j = 0; j < kFastRB; ++j) {
-                    const int row = (wave + j * nwave) * 16 + (lane & 15);
-                    const double *__restrict__ crow = A.creg + (size_t)min(row, nrow - 1) * NL;
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) {
-                        const int d = 4 * ks + (lane >> 4);
-                        ca[j][ks] = (row < nrow && d < NL) ? crow[d] : 0.0;
-                    }
-                }
                 __syncthreads();
-                mfma_d4 acc[kFastRB];
+                if (p0 + (int64_t)wave * 128 < p1) fetch(p0 + (int64_t)wave * 128, p1);   // first pair block of batch 0
+                mfma_d4 acc[kPairRB];
 #pragma unroll
-                for (int j = 0; j < kFastRB; ++j) acc[j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < kPairRB; ++j) acc[j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
                 const int q = lane & 15;
 #pragma unroll
-                for (int j = 0; j < kFastRB; ++j) {
+                for (int j = 0; j < kPairRB; ++j) {
                     const int rb = wave + j * nwave;
                     if (rb >= nblk) continue;              // uniform across the wave
 #pragma unroll
@@ -1380,7 +1405,7 @@ __global__ __launch_bounds__(kFastRow) void k_local_pairs(LocalArgs A, PairLists
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < kFastRB; ++j) {
+                for (int j = 0; j < kPairRB; ++j) {
                     const int rb = wave + j * nwave;
                     if (rb >= nblk || q >= ns) continue;
 #pragma unroll
@@ -1397,35 +1422,29 @@ __global__ __launch_bounds__(kFastRow) void k_local_pairs(LocalArgs A, PairLists
                     for (int t = tid; t < ntb; t += bd) tacc[t] = 0.0;
                     __syncthreads();
                 }
-                const int64_t seg = seg0 + (int64_t)i * nb + b;
-                const int64_t p0 = P.off[seg * kFastSrc], p1 = P.off[(seg + 1) * kFastSrc];
+                const int64_t seg = seg_i + b;
+                const int64_t bp0 = b ? uniform64(P.soff[seg]) : p0, bp1 = b ? uniform64(P.soff[seg + 1]) : p1;
                 const int64_t stride = (int64_t)nwave * 128;
-                int64_t base = p0 + (int64_t)wave * 128;
+                int64_t base = bp0 + (int64_t)wave * 128;
                 // the next block's words and coordinates are loaded while this block is evaluated
-                uint32_t nw0 = 0u, nw1 = 0u;
-                double nx0 = 0.0, nx1 = 0.0;
-                auto fetch = [&](int64_t bs) {
-                    const int64_t e0 = bs + lane, e1 = e0 + 64;
-                    nw0 = e0 < p1 ? P.ent[e0] : 0u;
-                    nx0 = e0 < p1 ? P.x[e0] : 0.0;
-                    nw1 = e1 < p1 ? P.ent[e1] : 0u;
-                    nx1 = e1 < p1 ? P.x[e1] : 0.0;
-                };
-                if (base < p1) fetch(base);
-                for (; base < p1; base += stride) {
+                // (batch 0's first block was loaded before the profile synthesis)
+                if (b && base < bp1) fetch(base, bp1);
+                for (; base < bp1; base += stride) {
                     const uint32_t w0 = nw0, w1 = nw1;
                     const double x0 = nx0, x1 = nx1;
-                    const bool v0 = base + lane < p1, v1 = base + 64 + lane < p1;
-                    if (base + stride < p1) fetch(base + stride);
+                    const bool v0 = base + lane < bp1, v1 = base + 64 + lane < bp1;
+                    if (base + stride < bp1) fetch(base + stride, bp1);
                     double u0, u1;
                     cheb_eval2(psi + (int)((w0 >> 16) & 15u) * psiSrc + (int)(w0 >> 20) * kPsiRow, x0,
                                psi + (int)((w1 >> 16) & 15u) * psiSrc + (int)(w1 >> 20) * kPsiRow, x1, u0, u1);
-                    if (v0) atomicAdd(&tacc[w0 & 0xffffu], u0);
-                    if (v1) atomicAdd(&tacc[w1 & 0xffffu], u1);
+                    // padding lanes add 0 to distinct sums (no same-address atomics, no branch around
+                    // the two sums, which would then be evaluated one after the other)
+                    atomicAdd(&tacc[v0 ? (int)(w0 & 0xffffu) : lane], v0 ? u0 : 0.0);
+                    atomicAdd(&tacc[v1 ? (int)(w1 & 0xffffu) : 64 + lane], v1 ? u1 : 0.0);
                 }
                 // pairs with r < dt/2: one wavefront per pair, lanes over levels
-                const int64_t q0 = P.doff[seg * kFastSrc], q1 = P.doff[(seg + 1) * kFastSrc];
-                for (int64_t q = q0 + wave; q < q1; q += nwave) {
+                const int64_t bq0 = b ? uniform64(P.sdoff[seg]) : q0, bq1 = b ? uniform64(P.sdoff[seg + 1]) : q1;
+                for (int64_t q = bq0 + wave; q < bq1; q += nwave) {
                     const uint32_t wq = P.dent[q];
                     const double r = P.dr[q];
                     const int sidx = (int)((wq >> 16) & 15u);
@@ -1720,9 +1739,13 @@ static LocalArgs local_args(const Plan &p)
 static PairLists pair_lists(const Plan &p)
 {
     PairLists P;
-    P.cseg = p.d_pair_cseg;
+    P.wrec = p.d_pair_wrec;
+    P.wseg = p.d_pair_wseg;
+    P.n_work = (int)p.pair_n_work;
     P.off = p.d_pair_off;
     P.doff = p.d_pair_doff;
+    P.soff = p.d_seg_off;
+    P.sdoff = p.d_seg_doff;
     P.ent = p.d_pair_ent;
     P.x = p.d_pair_x;
     P.dent = p.d_pair_dent;
@@ -1742,7 +1765,7 @@ hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt)
     B.dent = p.d_pair_dent;
     B.dr = p.d_pair_dr;
     B.fill = fill ? 1 : 0;
-    const unsigned grid = (unsigned)std::min(p.ncell * p.ncell, 4096);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, 4096));
     hipLaunchKernelGGL(k_pairs_build, dim3(grid), dim3(256), 0, p.stream, A, P, B, p.dt, (int)p.W);
     return hipGetLastError();
 }
@@ -1752,8 +1775,8 @@ hipError_t launch_local(Plan &p)
     const LocalArgs A = local_args(p);
     if (p.local_pairs) {
         const int nrow = p.n_reg * kChebDeg;
-        const unsigned threads = (unsigned)((nrow + 63) / 64 * 64);
-        const unsigned grid = (unsigned)std::min(p.ncell * p.ncell, 2 * 256);
+        const unsigned threads = kPairThreads;   // one workgroup per compute unit
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, p.n_cu));
         const size_t lds = (size_t)kFastSrc * (p.n_reg * (kChebDeg + 1) + 1) * sizeof(double);
         const PairLists P = pair_lists(p);
         if (p.g.nlev == 35)
