@@ -94,7 +94,8 @@ typedef struct {
     int32_t nufft_w;       /* spreading kernel width in grid points */
     int32_t W, p, lookahead, n_levels; /* window steps, interp order, delay, sigma levels in the local part */
     int32_t level_min;     /* most negative delay level used by the local part (= -lookahead) */
-    int32_t n_subpanels, cheb_degree;
+    int32_t n_subpanels;
+    int32_t cheb_degree;   /* Chebyshev terms per regular sub-panel evaluated by the local kernel */
     int64_t M, Nx;
     int64_t n_local_pairs; /* source-target pairs with 0 < r < delta */
     int64_t sigma_depth;   /* slots in the sigma history ring */

@@ -603,6 +603,32 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_panel_l2n, LT.panel_l2n);
     if (p.local_fast && p.W <= 64 && p.n_reg * kChebDeg <= kPairThreads / 64 * kPairRB * 16 && p.opts.local_pairs == 0)
         build_pair_lists(p, cell_start, tcell_start);
+    if (p.local_pairs && p.precision == WFP2D_PREC_MIXED) {
+        // Mixed precision: evaluate only the leading terms of each regular panel's series when
+        // the dropped ones sum to at most 1e-3 tol, relative to the largest coefficient (the
+        // scale of the fit criterion of the tables).  Measured, the field then moves by about
+        // ten times that bound, two orders of magnitude below tol; FP64 plans use every
+        // stored term.
+        const int nl = LT.nlev, D = kChebDeg;
+        double gmax = 0.0;
+        for (double v : LT.coef) gmax = std::max(gmax, std::fabs(v));
+        for (int nt : {12, 14, 16}) {
+            double tail = 0.0;
+            for (int k = 0; k < p.n_reg; ++k) {
+                double t = 0.0;
+                for (int c = nt; c < D; ++c) {
+                    double cm = 0.0;
+                    for (int d = 0; d < nl; ++d) cm = std::max(cm, std::fabs(LT.coef[((size_t)k * nl + d) * D + c]));
+                    t += cm;
+                }
+                tail = std::max(tail, t);
+            }
+            if (tail <= 1e-3 * p.tol * gmax) {
+                p.local_terms = nt;
+                break;
+            }
+        }
+    }
     // local-pair count (reported; without pair lists the local kernel finds pairs through the cell lists)
     if (!p.local_pairs) {
         int64_t cnt = 0;
@@ -1005,7 +1031,7 @@ wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
     info->n_levels = p.g.nlev;
     info->level_min = p.g.lev_min;
     info->n_subpanels = p.n_sub;
-    info->cheb_degree = kChebDeg;
+    info->cheb_degree = p.local_pairs ? p.local_terms : kChebDeg;
     info->M = p.M;
     info->Nx = p.Nx;
     info->n_local_pairs = p.n_local_pairs;

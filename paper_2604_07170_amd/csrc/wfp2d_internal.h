@@ -169,6 +169,7 @@ struct Plan {
     int32_t dy_base = 0, n_dy = 0;
     // pair lists of the local part (built once when they fit; see k_pairs_build)
     bool local_pairs = false;
+    int32_t local_terms = kChebDeg;   // leading Chebyshev terms of each regular panel used by the pair kernel
     int64_t pair_bytes = 0;
     int64_t pair_n_work = 0;          // cells with sources and with targets in their 5 x 5 block
     int32_t *d_pair_wrec = nullptr;   // their records: s0, s1, rbeg[5], rcum[6], padding (16 int32)

@@ -734,13 +734,14 @@ __device__ __forceinline__ double cheb_eval(const double *c, double x)
     return fma(x, b1, c[0] - b2);
 }
 
-// two independent Clenshaw recurrences interleaved (instruction-level parallelism)
-__device__ __forceinline__ void cheb_eval2(const double *c0, double x0, const double *c1, double x1, double &v0, double &v1)
+// two independent Clenshaw recurrences of NT terms interleaved (instruction-level parallelism)
+template <int NT>
+__device__ __forceinline__ void cheb_eval2n(const double *c0, double x0, const double *c1, double x1, double &v0, double &v1)
 {
     double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
     const double t0 = 2.0 * x0, t1 = 2.0 * x1;
 #pragma unroll
-    for (int k = kChebDeg - 1; k >= 1; --k) {
+    for (int k = NT - 1; k >= 1; --k) {
         const double a0 = fma(t0, a1, c0[k] - a2);
         const double b0 = fma(t1, b1, c1[k] - b2);
         a2 = a1;
@@ -750,6 +751,11 @@ __device__ __forceinline__ void cheb_eval2(const double *c0, double x0, const do
     }
     v0 = fma(x0, a1, c0[0] - a2);
     v1 = fma(x1, b1, c1[0] - b2);
+}
+
+__device__ __forceinline__ void cheb_eval2(const double *c0, double x0, const double *c1, double x1, double &v0, double &v1)
+{
+    cheb_eval2n<kChebDeg>(c0, x0, c1, x1, v0, v1);
 }
 
 __device__ __forceinline__ double sub_coord(const SubPanel &sp, double r)
@@ -1318,7 +1324,9 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <int NL>
+// NL sigma levels; NTERM leading Chebyshev terms of each regular panel's series (of kChebDeg
+// stored), enough for the plan's tolerance
+template <int NL, int NTERM>
 __global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
 {
     const int64_t m = step[0] - g.lookahead;
@@ -1329,7 +1337,8 @@ __global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairL
     __shared__ int rec[kCellRec];
 
     const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wave = uniform(tid >> 6), nwave = bd >> 6;
-    const int D = kChebDeg, nrow = A.n_reg * kChebDeg, psiSrc = psi_src_stride(A.n_reg);
+    constexpr int D = NTERM, kRow = NTERM + 1;        // psi row stride (odd: rows spread over the LDS banks)
+    const int nrow = A.n_reg * D, psiSrc = A.n_reg * kRow + 1;
     double *psi = fast_lds;
     constexpr int KS = (NL + 3) / 4;
     const int nblk = (nrow + 15) / 16;
@@ -1343,7 +1352,8 @@ __global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairL
 #pragma unroll
     for (int j = 0; j < kPairRB; ++j) {
         const int row = (wave + j * nwave) * 16 + (lane & 15);
-        const double *__restrict__ crow = A.creg + (size_t)min(row, nrow - 1) * NL;
+        const int rr = min(row, nrow - 1);
+        const double *__restrict__ crow = A.creg + (size_t)((rr / D) * kChebDeg + rr % D) * NL;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int d = 4 * ks + (lane >> 4);
@@ -1411,7 +1421,7 @@ __global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairL
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = rb * 16 + (lane >> 4) + 4 * r;
-                        if (row < nrow) psi[q * psiSrc + (row / D) * kPsiRow + row % D] = acc[j][r];
+                        if (row < nrow) psi[q * psiSrc + (row / D) * kRow + row % D] = acc[j][r];
                     }
                 }
             }
@@ -1435,8 +1445,8 @@ __global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairL
                     const bool v0 = base + lane < bp1, v1 = base + 64 + lane < bp1;
                     if (base + stride < bp1) fetch(base + stride, bp1);
                     double u0, u1;
-                    cheb_eval2(psi + (int)((w0 >> 16) & 15u) * psiSrc + (int)(w0 >> 20) * kPsiRow, x0,
-                               psi + (int)((w1 >> 16) & 15u) * psiSrc + (int)(w1 >> 20) * kPsiRow, x1, u0, u1);
+                    cheb_eval2n<D>(psi + (int)((w0 >> 16) & 15u) * psiSrc + (int)(w0 >> 20) * kRow, x0,
+                                   psi + (int)((w1 >> 16) & 15u) * psiSrc + (int)(w1 >> 20) * kRow, x1, u0, u1);
                     // padding lanes add 0 to distinct sums (no same-address atomics, no branch around
                     // the two sums, which would then be evaluated one after the other)
                     atomicAdd(&tacc[v0 ? (int)(w0 & 0xffffu) : lane], v0 ? u0 : 0.0);
@@ -1452,7 +1462,7 @@ __global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairL
                     const double xc = sub_coord(A.subs[sub], r);
                     double v = 0.0;
                     for (int d = lane; d < NL; d += 64)
-                        v = fma(cheb_eval(A.cheb + ((size_t)sub * NL + d) * D, xc), sigs[sidx * NL + d], v);
+                        v = fma(cheb_eval(A.cheb + ((size_t)sub * NL + d) * kChebDeg, xc), sigs[sidx * NL + d], v);
                     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
                     if (lane == 0) atomicAdd(&tacc[wq & 0xffffu], v);
                 }
@@ -1563,8 +1573,12 @@ hipError_t kernel_setup(Plan &)
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_local_fast<35>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
     if ((e = hipFuncSetAttribute((const void *)k_local_fast<43>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
-    if ((e = hipFuncSetAttribute((const void *)k_local_pairs<35>, hipFuncAttributeMaxDynamicSharedMemorySize, pbytes))) return e;
-    return hipFuncSetAttribute((const void *)k_local_pairs<43>, hipFuncAttributeMaxDynamicSharedMemorySize, pbytes);
+    const void *pk[] = {(const void *)k_local_pairs<35, 12>, (const void *)k_local_pairs<35, 14>, (const void *)k_local_pairs<35, 16>,
+                        (const void *)k_local_pairs<35, 20>, (const void *)k_local_pairs<43, 12>, (const void *)k_local_pairs<43, 14>,
+                        (const void *)k_local_pairs<43, 16>, (const void *)k_local_pairs<43, 20>};
+    for (const void *k : pk)
+        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, pbytes))) return e;
+    return hipSuccess;
 }
 
 static size_t fft_lds_bytes(const Plan &p)
@@ -1777,12 +1791,18 @@ hipError_t launch_local(Plan &p)
         const int nrow = p.n_reg * kChebDeg;
         const unsigned threads = kPairThreads;   // one workgroup per compute unit
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, p.n_cu));
-        const size_t lds = (size_t)kFastSrc * (p.n_reg * (kChebDeg + 1) + 1) * sizeof(double);
+        const size_t lds = (size_t)kFastSrc * (p.n_reg * (p.local_terms + 1) + 1) * sizeof(double);
         const PairLists P = pair_lists(p);
-        if (p.g.nlev == 35)
-            hipLaunchKernelGGL(k_local_pairs<35>, dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g);
-        else
-            hipLaunchKernelGGL(k_local_pairs<43>, dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g);
+#define WFP2D_LAUNCH_PAIRS(NLV, NTV) \
+    hipLaunchKernelGGL((k_local_pairs<NLV, NTV>), dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g)
+        const bool l35 = p.g.nlev == 35;
+        switch (p.local_terms) {
+        case 12: if (l35) WFP2D_LAUNCH_PAIRS(35, 12); else WFP2D_LAUNCH_PAIRS(43, 12); break;
+        case 14: if (l35) WFP2D_LAUNCH_PAIRS(35, 14); else WFP2D_LAUNCH_PAIRS(43, 14); break;
+        case 16: if (l35) WFP2D_LAUNCH_PAIRS(35, 16); else WFP2D_LAUNCH_PAIRS(43, 16); break;
+        default: if (l35) WFP2D_LAUNCH_PAIRS(35, 20); else WFP2D_LAUNCH_PAIRS(43, 20); break;
+        }
+#undef WFP2D_LAUNCH_PAIRS
         return hipGetLastError();
     }
     if (p.local_fast) {

@@ -1,9 +1,11 @@
 """The local part from stored pair lists (the default) against the per-step pair
 search, and against the oracle (GPU).
 
-Both paths evaluate the same pairs with the same panel, coordinate and
-Clenshaw sums (Sec. 6, eq. local2); only the order of the per-target additions
-differs, so their fields agree to rounding.  A workload with targets placed
+Both paths evaluate the same pairs with the same panel and coordinate (Sec. 6,
+eq. local2).  With the same number of Chebyshev terms only the order of the
+per-target additions differs, so the fields agree to rounding; a mixed-precision
+plan may drop trailing terms whose sum is at most 1e-3 tol of the largest
+coefficient, and the fields must then still agree to 0.05 tol.  A workload with targets placed
 within dt/2 of sources covers the dyadic sub-panels, which have lists of
 their own.
 """
@@ -40,6 +42,11 @@ def _lockstep(w, precision, steps, **kw):
     return ia, ib, out_a, out_b
 
 
+def _agreement(ia, ib, w):
+    """Bound on the relative difference of the two paths' fields."""
+    return 1e-12 if ia["cheb_degree"] == ib["cheb_degree"] else 0.05 * w.tol
+
+
 def _near_coincident(n_src=256, seed=31):
     """Uniform sources, 4 wavelengths (dt = 0.05); each target sits at a distance in
     [0.01, 0.9] dt from its source, so that both dyadic (r < dt/2) and regular pairs occur."""
@@ -64,11 +71,13 @@ def test_pair_lists_match_pair_search_config0(precision):
     ia, ib, ua, ub = _lockstep(w, precision, steps)
     assert ia["local_path"] == 2 and ia["local_pair_bytes"] > 0
     assert ib["local_path"] == 1 and ib["local_pair_bytes"] == 0
+    assert ib["cheb_degree"] == 20 and (ia["cheb_degree"] == 20 if precision == "fp64" else ia["cheb_degree"] <= 20)
     assert abs(ia["n_local_pairs"] - ib["n_local_pairs"]) <= max(2, 1e-6 * ib["n_local_pairs"])
+    print(f"config0 {precision}: Chebyshev terms {ia['cheb_degree']} (pair lists) vs {ib['cheb_degree']} (search)")
     for m in sorted(steps):
         d = rel_l2(ua[m], ub[m])
         print(f"config0 {precision} step {m}: pair lists vs search rel diff {d:.2e}")
-        assert d <= 1e-12
+        assert d <= _agreement(ia, ib, w)
 
 
 def test_pair_lists_match_pair_search_config2():
@@ -82,7 +91,7 @@ def test_pair_lists_match_pair_search_config2():
         assert np.isfinite(ua[m]).all() and np.linalg.norm(ub[m]) > 0
         d = rel_l2(ua[m], ub[m])
         print(f"config2 mixed step {m}: pair lists vs search rel diff {d:.2e}")
-        assert d <= 1e-12
+        assert d <= _agreement(ia, ib, w)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -95,7 +104,7 @@ def test_pair_lists_dyadic_pairs_against_oracle(precision):
     for m in sorted(steps):
         assert np.isfinite(ua[m]).all() and np.linalg.norm(ub[m]) > 0
         d = rel_l2(ua[m], ub[m])
-        assert d <= 1e-12, d
+        assert d <= _agreement(ia, ib, w), d
     U = np.array([ua[m] for m in sorted(steps)]).T
     Uo = oracle_field(w, ia, idx, sorted(steps), self_mode=0)
     err = rel_l2(U, Uo)
