@@ -331,7 +331,9 @@ def main():
                    "timed_steps": f"{args.warmup + 1}..{args.warmup + K} (reported u at t_{step_reported - K + 1}.."
                                   f"t_{step_reported})", "precision": args.precision,
                    "n_modes": info["n_modes"], "nf": info["nf"], "local_pairs": info["n_local_pairs"],
-                   "spread_tile": list(pa.Wfp2d.SPREAD_TILES[plan.info()["spread_tile"]])},
+                   "spread_tile": list(pa.Wfp2d.SPREAD_TILES[plan.info()["spread_tile"]]),
+                   "local_path": ["generic", "pair search", "pair lists"][info["local_path"]],
+                   "cheb_terms": info["cheb_degree"]},
         "roofline": roof,
         "hbm_roofline_step_frac": round(step_hbm_frac, 4),
         "stages": per_stage,

@@ -235,7 +235,8 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
         doff[s + 1] = doff[s] + dcnt[s];
     }
     const int64_t npair = off.back(), ndy = doff.back();
-    const int64_t bytes = (npair + ndy) * (int64_t)(sizeof(uint32_t) + sizeof(double)) +
+    const int64_t bytes = npair * (int64_t)(sizeof(uint32_t) + sizeof(double)) +
+                          ndy * (int64_t)(sizeof(uint32_t) + p.g.nlev * sizeof(double)) +
                           2 * (nslot + 1 + nslot / kFastSrc + 1) * (int64_t)sizeof(int64_t);
     size_t free_b = 0, total_b = 0;
     hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
@@ -266,7 +267,7 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
     p.d_pair_ent = p.alloc<uint32_t>(npair);
     p.d_pair_x = p.alloc<double>(npair);
     p.d_pair_dent = p.alloc<uint32_t>(ndy);
-    p.d_pair_dr = p.alloc<double>(ndy);
+    p.d_pair_dw = p.alloc<double>(ndy * p.g.nlev);
     hip_check(launch_pairs_build(p, true, nullptr, nullptr), "pair fill");
     hip_check(hipStreamSynchronize(p.stream), "pair fill");
     p.local_pairs = true;

@@ -28,7 +28,8 @@ constexpr int kFastSrc = 16;       // fast local kernel: sources per chunk
 constexpr int kFastRow = 512;      //   max coefficient rows (regular sub-panels x Chebyshev terms)
 constexpr int kPairTB = 1024;      // pair-list local kernel: targets per batch (LDS sums)
 constexpr int kPairRec = 16;       //   int32 per work-cell record
-constexpr int kPairThreads = 1024; //   threads per workgroup (16 waves, one workgroup per CU)
+constexpr int kPairThreads = 1024; //   threads per workgroup: 16 waves, one workgroup per CU, or
+constexpr int kPairThreadsHalf = 512; //   8 waves, two per CU, when the rows fit 8 x kPairRB blocks
 constexpr int kPairRB = 2;         //   16-row blocks of the coefficient table per wave
 constexpr int kFastOwn = 4;        //   targets owned per thread
 
@@ -176,9 +177,10 @@ struct Plan {
     int64_t *d_pair_wseg = nullptr;   // first segment of each work cell, [n_work + 1]
     int64_t *d_pair_off = nullptr, *d_pair_doff = nullptr;   // [n_seg * kFastSrc + 1]
     int64_t *d_seg_off = nullptr, *d_seg_doff = nullptr;     // first pair of each segment, [n_seg + 1]
+    double *d_pair_dw = nullptr;      // eta_d(r) of each pair with r < dt/2, [n_dy_pairs][nlev]
     int32_t n_cu = 256;               // compute units of the device (persistent grids)
     uint32_t *d_pair_ent = nullptr, *d_pair_dent = nullptr;
-    double *d_pair_x = nullptr, *d_pair_dr = nullptr;
+    double *d_pair_x = nullptr;
 
     std::string err;
 

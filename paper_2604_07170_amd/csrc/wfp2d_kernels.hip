@@ -1232,14 +1232,14 @@ struct PairLists {
     const uint32_t *ent;          // regular pairs: t | s << 16 | k << 20
     const double *x;              //   and their Chebyshev coordinates
     const uint32_t *dent;         // pairs with r < dt/2: t | s << 16
-    const double *dr;             //   and their distances
+    const double *dw;             //   and their weights eta_d(r), d < nlev (dyadic sub-panel tables)
 };
 
 struct PairBuild {
     int64_t *cnt, *dcnt;          // count pass: pairs per (segment, source in chunk)
     uint32_t *ent, *dent;         // fill pass: the lists, at the offsets of PairLists
-    double *x, *dr;
-    int fill;
+    double *x, *dw;
+    int fill, nlev;
 };
 
 // targets of a cell's 5 x 5 block: five runs of the sorted target order (rows
@@ -1300,7 +1300,11 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
                     if (B.fill && dya) {
                         const int64_t e = o_dy + c_dy + __popcll(md & below);
                         B.dent[e] = (uint32_t)t | ((uint32_t)sl << 16);
-                        B.dr[e] = sqrt(r2);
+                        const double r = sqrt(r2);
+                        const int sub = dyadic_sub(A, r * A.inv_dt);
+                        const double xc = sub_coord(A.subs[sub], r);
+                        for (int d = 0; d < B.nlev; ++d)
+                            B.dw[e * B.nlev + d] = cheb_eval(A.cheb + ((size_t)sub * B.nlev + d) * kChebDeg, xc);
                     }
                     c_reg += __popcll(mr);
                     c_dy += __popcll(md);
@@ -1325,9 +1329,9 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 }
 
 // NL sigma levels; NTERM leading Chebyshev terms of each regular panel's series (of kChebDeg
-// stored), enough for the plan's tolerance
-template <int NL, int NTERM>
-__global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
+// stored), enough for the plan's tolerance; TPB threads per workgroup, 1024 / TPB workgroups per CU
+template <int NL, int NTERM, int TPB>
+__global__ __launch_bounds__(TPB, 1024 / TPB) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
 {
     const int64_t m = step[0] - g.lookahead;
     extern __shared__ double fast_lds[];              // psi [kFastSrc][psiSrc]
@@ -1452,19 +1456,16 @@ __global__ __launch_bounds__(kPairThreads) void k_local_pairs(LocalArgs A, PairL
                     atomicAdd(&tacc[v0 ? (int)(w0 & 0xffffu) : lane], v0 ? u0 : 0.0);
                     atomicAdd(&tacc[v1 ? (int)(w1 & 0xffffu) : 64 + lane], v1 ? u1 : 0.0);
                 }
-                // pairs with r < dt/2: one wavefront per pair, lanes over levels
+                // pairs with r < dt/2: one lane per pair, sum over levels with the stored weights
                 const int64_t bq0 = b ? uniform64(P.sdoff[seg]) : q0, bq1 = b ? uniform64(P.sdoff[seg + 1]) : q1;
-                for (int64_t q = bq0 + wave; q < bq1; q += nwave) {
+                for (int64_t q = bq0 + (int64_t)wave * 64 + lane; q < bq1; q += (int64_t)nwave * 64) {
                     const uint32_t wq = P.dent[q];
-                    const double r = P.dr[q];
-                    const int sidx = (int)((wq >> 16) & 15u);
-                    const int sub = dyadic_sub(A, r * A.inv_dt);
-                    const double xc = sub_coord(A.subs[sub], r);
+                    const double *__restrict__ wd = P.dw + q * NL;
+                    const double *sg = sigs + (int)((wq >> 16) & 15u) * NL;
                     double v = 0.0;
-                    for (int d = lane; d < NL; d += 64)
-                        v = fma(cheb_eval(A.cheb + ((size_t)sub * NL + d) * kChebDeg, xc), sigs[sidx * NL + d], v);
-                    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-                    if (lane == 0) atomicAdd(&tacc[wq & 0xffffu], v);
+#pragma unroll 5
+                    for (int d = 0; d < NL; ++d) v = fma(wd[d], sg[d], v);
+                    atomicAdd(&tacc[wq & 0xffffu], v);
                 }
                 __syncthreads();
                 if (nb > 1 || i == nch - 1) {
@@ -1573,9 +1574,15 @@ hipError_t kernel_setup(Plan &)
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_local_fast<35>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
     if ((e = hipFuncSetAttribute((const void *)k_local_fast<43>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
-    const void *pk[] = {(const void *)k_local_pairs<35, 12>, (const void *)k_local_pairs<35, 14>, (const void *)k_local_pairs<35, 16>,
-                        (const void *)k_local_pairs<35, 20>, (const void *)k_local_pairs<43, 12>, (const void *)k_local_pairs<43, 14>,
-                        (const void *)k_local_pairs<43, 16>, (const void *)k_local_pairs<43, 20>};
+    const void *pk[] = {
+#define WFP2D_PAIR_KERNELS(NLV) \
+        (const void *)k_local_pairs<NLV, 12, kPairThreadsHalf>, (const void *)k_local_pairs<NLV, 14, kPairThreadsHalf>, \
+        (const void *)k_local_pairs<NLV, 16, kPairThreadsHalf>, (const void *)k_local_pairs<NLV, 12, kPairThreads>, \
+        (const void *)k_local_pairs<NLV, 14, kPairThreads>, (const void *)k_local_pairs<NLV, 16, kPairThreads>, \
+        (const void *)k_local_pairs<NLV, 20, kPairThreads>
+        WFP2D_PAIR_KERNELS(35), WFP2D_PAIR_KERNELS(43)
+#undef WFP2D_PAIR_KERNELS
+    };
     for (const void *k : pk)
         if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, pbytes))) return e;
     return hipSuccess;
@@ -1763,7 +1770,7 @@ static PairLists pair_lists(const Plan &p)
     P.ent = p.d_pair_ent;
     P.x = p.d_pair_x;
     P.dent = p.d_pair_dent;
-    P.dr = p.d_pair_dr;
+    P.dw = p.d_pair_dw;
     return P;
 }
 
@@ -1777,8 +1784,9 @@ hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt)
     B.ent = p.d_pair_ent;
     B.x = p.d_pair_x;
     B.dent = p.d_pair_dent;
-    B.dr = p.d_pair_dr;
+    B.dw = p.d_pair_dw;
     B.fill = fill ? 1 : 0;
+    B.nlev = p.g.nlev;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, 4096));
     hipLaunchKernelGGL(k_pairs_build, dim3(grid), dim3(256), 0, p.stream, A, P, B, p.dt, (int)p.W);
     return hipGetLastError();
@@ -1788,20 +1796,25 @@ hipError_t launch_local(Plan &p)
 {
     const LocalArgs A = local_args(p);
     if (p.local_pairs) {
-        const int nrow = p.n_reg * kChebDeg;
-        const unsigned threads = kPairThreads;   // one workgroup per compute unit
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, p.n_cu));
+        const int nrow = p.n_reg * p.local_terms;
+        // two 8-wave workgroups per CU (their phases overlap) when 8 waves cover the coefficient
+        // rows, else one 16-wave workgroup per CU
+        const bool half = p.local_terms < kChebDeg && nrow <= kPairThreadsHalf / 64 * kPairRB * 16;
+        const unsigned threads = half ? kPairThreadsHalf : kPairThreads;
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, (int64_t)p.n_cu * (half ? 2 : 1)));
         const size_t lds = (size_t)kFastSrc * (p.n_reg * (p.local_terms + 1) + 1) * sizeof(double);
         const PairLists P = pair_lists(p);
-#define WFP2D_LAUNCH_PAIRS(NLV, NTV) \
-    hipLaunchKernelGGL((k_local_pairs<NLV, NTV>), dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g)
-        const bool l35 = p.g.nlev == 35;
+#define WFP2D_LAUNCH_PAIRS(NLV, NTV, TPB) \
+    hipLaunchKernelGGL((k_local_pairs<NLV, NTV, TPB>), dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g)
+#define WFP2D_LAUNCH_PAIRS_NL(NTV, TPB) \
+    do { if (p.g.nlev == 35) WFP2D_LAUNCH_PAIRS(35, NTV, TPB); else WFP2D_LAUNCH_PAIRS(43, NTV, TPB); } while (0)
         switch (p.local_terms) {
-        case 12: if (l35) WFP2D_LAUNCH_PAIRS(35, 12); else WFP2D_LAUNCH_PAIRS(43, 12); break;
-        case 14: if (l35) WFP2D_LAUNCH_PAIRS(35, 14); else WFP2D_LAUNCH_PAIRS(43, 14); break;
-        case 16: if (l35) WFP2D_LAUNCH_PAIRS(35, 16); else WFP2D_LAUNCH_PAIRS(43, 16); break;
-        default: if (l35) WFP2D_LAUNCH_PAIRS(35, 20); else WFP2D_LAUNCH_PAIRS(43, 20); break;
+        case 12: if (half) WFP2D_LAUNCH_PAIRS_NL(12, kPairThreadsHalf); else WFP2D_LAUNCH_PAIRS_NL(12, kPairThreads); break;
+        case 14: if (half) WFP2D_LAUNCH_PAIRS_NL(14, kPairThreadsHalf); else WFP2D_LAUNCH_PAIRS_NL(14, kPairThreads); break;
+        case 16: if (half) WFP2D_LAUNCH_PAIRS_NL(16, kPairThreadsHalf); else WFP2D_LAUNCH_PAIRS_NL(16, kPairThreads); break;
+        default: WFP2D_LAUNCH_PAIRS_NL(20, kPairThreads); break;
         }
+#undef WFP2D_LAUNCH_PAIRS_NL
 #undef WFP2D_LAUNCH_PAIRS
         return hipGetLastError();
     }
