@@ -289,7 +289,9 @@ def main():
     else:
         roof = {"bound": "alu", "kernel": pa.Wfp2d.KERNELS[pa.Wfp2d.STAGES.index(dom)], "achieved": d["achieved_TFLOPs"],
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": d["frac"], "traffic": None}
-        roof["traffic"] = measured_traffic("k_local_fast" if roof["kernel"] == "k_local" else roof["kernel"])
+        if roof["kernel"] == "k_local":          # the local-part kernel the plan runs
+            roof["kernel"] = ["k_local", "k_local_fast", "k_local_pairs"][info["local_path"]]
+        roof["traffic"] = measured_traffic(roof["kernel"])
     hbm_bytes = sum(costs[s][1] for s in per_stage if costs[s][0] == "hbm")
     step_hbm_frac = hbm_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS
 
