@@ -134,3 +134,39 @@ def test_config2_sampled_with_far_history(precision):
     err = rel_l2(U, Uo)
     print(f"config2 {precision}: rel L2 {err:.3e} over {U.size} samples (|u| ~ {np.abs(Uo).max():.2f})")
     assert err <= TOL_E2E
+
+
+def test_config4_full_size_sampled():
+    """10^6 uniform sources = targets, 300 wavelengths, in the configuration the benchmark
+    times (mixed precision, stored pair lists, default Chebyshev terms): 2 seeded targets x
+    2 steps after the far-history onset (step LA + W = 4316) against the oracle, which sums
+    all 10^6 sources for each sample."""
+    import time
+    import torch
+    import paper_2604_07170_amd as pa
+    from wfp_workloads import config
+    w = config(4)
+    steps = [4400, 4500]
+    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision="mixed", interp_order=w.p)
+    info = plan.info()
+    assert info["local_path"] == 2 and steps[0] > info["LA"] + info["W"]
+    L = info["lookahead"]
+    dev = torch.device("cuda", 0)
+    params = w.torch_params(dev)
+    tg = np.sort(np.random.default_rng(14).choice(w.Nx, size=2, replace=False))
+    u = torch.empty(w.Nx, dtype=torch.float64, device=dev)
+    got = {}
+    t0 = time.time()
+    for n in range(1, max(steps) + L + 1):
+        plan.step(w.sigma_torch(n * w.dt, dev, params))
+        if n - L in steps:
+            plan.evaluate(u)
+            got[n - L] = u[torch.as_tensor(tg, device=dev)].cpu().numpy()
+    torch.cuda.synchronize()
+    print(f"config4: {max(steps) + L} steps in {time.time() - t0:.1f} s", flush=True)
+    U = np.array([got[s] for s in steps]).T
+    t0 = time.time()
+    Uo = oracle_field(w, info, tg, steps)
+    err = rel_l2(U, Uo)
+    print(f"config4 mixed: rel L2 {err:.3e} over {U.size} samples (oracle {time.time() - t0:.1f} s)")
+    assert err <= TOL_E2E
