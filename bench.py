@@ -59,6 +59,26 @@ def measured_traffic(kernel: str):
     return None
 
 
+def copy_bandwidth(dev, gib: float = 1.0, reps: int = 5) -> float:
+    """Bytes read + written per second by a plain device-to-device copy of `gib` GiB
+    (torch's copy kernel), the practical HBM ceiling the stage fractions are read against."""
+    import torch
+    n = int(gib * 2**30) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return bw
+
+
 def stage_costs(info: dict) -> dict:
     """Algorithmic work of one launch of each stage: (bound, amount, unit).
 
@@ -209,6 +229,8 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     w = config(args.config)
+    copy_gbs = copy_bandwidth(dev)            # before the plan takes its memory
+    log(f"[bench] device copy: {copy_gbs:.0f} GB/s (read + write)")
     t0 = time.time()
     plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=args.precision, interp_order=w.p,
                     max_steps=args.warmup + args.steps + 32)
@@ -338,6 +360,7 @@ def main():
                    "cheb_terms": info["cheb_degree"]},
         "roofline": roof,
         "hbm_roofline_step_frac": round(step_hbm_frac, 4),
+        "hbm_copy_GBs": round(copy_gbs, 1),
         "stages": per_stage,
         "cpu_baseline": cpu,
         "sample_rel_err_vs_oracle": sample_err,

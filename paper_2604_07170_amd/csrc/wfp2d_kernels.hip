@@ -664,7 +664,9 @@ __global__ __launch_bounds__(256) void k_far(const int32_t *__restrict__ far_pk,
 // Eight lanes serve one target: lane r sums the stencil rows r, r + 8 (a
 // contiguous run of w grid values each, read through the cache), and the
 // eight partial sums are reduced with lane shuffles.  Targets are taken in
-// tile order, so neighbouring targets read neighbouring grid lines.
+// tile order, so neighbouring targets read neighbouring grid lines, and the
+// blocks are remapped so that each XCD (workgroups are dealt to the 8 XCDs in
+// turn) takes one contiguous range of targets and their lines stay in its L2.
 // Accumulation in FP64.
 // ---------------------------------------------------------------------------
 template <class R>
@@ -672,7 +674,9 @@ __global__ __launch_bounds__(256) void k_interp(const R *__restrict__ cgrid, con
                                                 const int32_t *__restrict__ tlist, double *__restrict__ uh, int w, int Lpad,
                                                 int64_t Nx)
 {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per_xcd = (int)(gridDim.x >> 3);      // the grid is a multiple of 8 blocks
+    const int lb = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    const int64_t gid = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t e = gid >> 3;
     const int r = (int)(gid & 7);
     double part = 0.0;
@@ -1721,7 +1725,7 @@ hipError_t launch_fft_rows2(Plan &p)
 hipError_t launch_interp(Plan &p)
 {
     const Geom &g = p.g;
-    const unsigned nb = (unsigned)((p.Nx * 8 + 255) / 256);
+    const unsigned nb = (unsigned)(((p.Nx * 8 + 255) / 256 + 7) / 8 * 8);   // padded to a multiple of 8 (XCD remap)
     if (p.precision == WFP2D_PREC_MIXED)
         hipLaunchKernelGGL(k_interp<float>, dim3(nb), dim3(256), 0, p.stream, (const float *)p.d_cgrid, p.d_tgt_base,
                            (const float *)p.d_tgt_wts, p.d_ttile_tgt, p.d_uh, g.w, g.Lpad, p.Nx);
