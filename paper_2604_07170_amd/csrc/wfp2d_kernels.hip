@@ -1334,26 +1334,34 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 
 // NL sigma levels; NTERM leading Chebyshev terms of each regular panel's series (of kChebDeg
 // stored), enough for the plan's tolerance; TPB threads per workgroup, 1024 / TPB workgroups per CU
+// (at least 4 waves per SIMD, so at most 128 VGPRs).
+// Software pipeline over the workgroup's chunks: while chunk i is synthesised and evaluated,
+// the sigma values and segment bounds of chunk i+1 are in flight (loaded right after chunk
+// i's sigma is stored, before anything that waits on memory), so the next chunk starts
+// without a memory wait.  sigma and the cell records are double-buffered in LDS.
 template <int NL, int NTERM, int TPB>
-__global__ __launch_bounds__(TPB, 1024 / TPB) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
+__global__ __launch_bounds__(TPB, 4) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
 {
+    constexpr int nwave = TPB / 64, KS = (NL + 3) / 4, NSIG = (kFastSrc * NL + TPB - 1) / TPB;
+    constexpr int D = NTERM, kRow = NTERM + 1;        // psi row stride (odd: rows spread over the LDS banks)
     const int64_t m = step[0] - g.lookahead;
     extern __shared__ double fast_lds[];              // psi [kFastSrc][psiSrc]
-    __shared__ double sigs[kFastSrc * NL];
-    __shared__ double tacc[kPairTB];
+    __shared__ double sigs[2][kFastSrc * NL];         // sigma of a chunk (buffer = chunk parity)
+    __shared__ double tacc[kPairTB];                  // per-target sums, zero between flushes
     __shared__ int64_t slot_base[NL];                 // ring offset of sigma level d at this step
-    __shared__ int rec[kCellRec];
+    __shared__ int recs[2][kCellRec];                 // work-cell records (buffer = cell parity)
 
-    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wave = uniform(tid >> 6), nwave = bd >> 6;
-    constexpr int D = NTERM, kRow = NTERM + 1;        // psi row stride (odd: rows spread over the LDS banks)
+    const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int nrow = A.n_reg * D, psiSrc = A.n_reg * kRow + 1;
-    double *psi = fast_lds;
-    constexpr int KS = (NL + 3) / 4;
     const int nblk = (nrow + 15) / 16;
-    const int *rbeg = rec + 2, *rcum = rec + 7;
-    // the record of this workgroup's next work cell is loaded one cell ahead
-    int nrec = (tid < kCellRec && (int)blockIdx.x < P.n_work) ? P.wrec[(int64_t)blockIdx.x * kCellRec + tid] : 0;
+    double *psi = fast_lds;
+    const int G = gridDim.x;
+    int wk = blockIdx.x;
+    if (wk >= P.n_work) return;                       // uniform, before any barrier
+
     if (tid < NL) slot_base[tid] = sig_slot(m, tid, g) * g.M;
+    for (int t = tid; t < kPairTB; t += TPB) tacc[t] = 0.0;
+    if (tid < kCellRec) recs[0][tid] = P.wrec[(int64_t)wk * kCellRec + tid];
     // A operands of this wave's row blocks of C (FP64 MFMA 16x16x4: lane holds
     // C[rb*16 + lane%16][4 ks + lane/16]), loaded once and kept in registers
     double ca[kPairRB][KS];
@@ -1368,6 +1376,32 @@ __global__ __launch_bounds__(TPB, 1024 / TPB) void k_local_pairs(LocalArgs A, Pa
             ca[j][ks] = (row < nrow && d < NL) ? crow[d] : 0.0;
         }
     }
+    __syncthreads();
+
+    // the next chunk's sigma values (NSIG per thread) and batch-0 segment bounds
+    double sreg[NSIG];
+    int64_t np0 = 0, np1 = 0, nq0 = 0, nq1 = 0;
+    auto prefetch = [&](int sb, int ns, int64_t seg) {
+#pragma unroll
+        for (int k = 0; k < NSIG; ++k) {
+            const int e = tid + k * TPB;
+            sreg[k] = 0.0;
+            if (e < ns * NL) {
+                const int sidx = e / NL, d = e - sidx * NL;
+                sreg[k] = A.sig[slot_base[d] + sb + sidx];
+            }
+        }
+        if (ns > 0) {
+            np0 = P.soff[seg];
+            np1 = P.soff[seg + 1];
+            nq0 = P.sdoff[seg];
+            nq1 = P.sdoff[seg + 1];
+        }
+    };
+    int c_sb = uniform(recs[0][0]), c_ns = min(kFastSrc, uniform(recs[0][1]) - c_sb);
+    prefetch(c_sb, c_ns, uniform64(P.wseg[wk]));
+    int nrec = (tid < kCellRec && wk + G < P.n_work) ? P.wrec[(int64_t)(wk + G) * kCellRec + tid] : 0;
+    int par = 0;
 
     // pair words and coordinates of a wave's next 128-pair block (loaded ahead of use)
     uint32_t nw0 = 0u, nw1 = 0u;
@@ -1380,72 +1414,78 @@ __global__ __launch_bounds__(TPB, 1024 / TPB) void k_local_pairs(LocalArgs A, Pa
         nx1 = e1 < pend ? P.x[e1] : 0.0;
     };
 
-    for (int wk = blockIdx.x; wk < P.n_work; wk += gridDim.x) {
-        if (tid < kCellRec) {
-            rec[tid] = nrec;
-            const int nk = wk + (int)gridDim.x;
-            nrec = nk < P.n_work ? P.wrec[(int64_t)nk * kCellRec + tid] : 0;
+    for (int j = 0; wk < P.n_work; ++j, wk += G) {
+        const int *rec = recs[j & 1];
+        const int *rbeg = rec + 2, *rcum = rec + 7;
+        if (j > 0 && tid < kCellRec) {                // its buffer was last read two cells ago
+            recs[j & 1][tid] = nrec;
+            nrec = wk + G < P.n_work ? P.wrec[(int64_t)(wk + G) * kCellRec + tid] : 0;
         }
-        __syncthreads();
-        const int s0 = uniform(rec[0]), s1 = uniform(rec[1]);
+        const bool more = wk + G < P.n_work;
+        const int next_s0 = more ? uniform(P.wrec[(int64_t)(wk + G) * kCellRec]) : 0;
+        const int next_s1 = more ? uniform(P.wrec[(int64_t)(wk + G) * kCellRec + 1]) : 0;
+        const int64_t next_seg0 = more ? uniform64(P.wseg[wk + G]) : 0;
         const int64_t seg0 = uniform64(P.wseg[wk]);
-        const int NT = uniform(rcum[5]), nb = (NT + kPairTB - 1) / kPairTB;
-        const int nch = (s1 - s0 + kFastSrc - 1) / kFastSrc;
-        if (nb == 1)                                   // one batch: the sums stay in LDS for the whole cell
-            for (int t = tid; t < NT; t += bd) tacc[t] = 0.0;
-        for (int i = 0; i < nch; ++i) {
-            const int sb = s0 + i * kFastSrc, ns = min(kFastSrc, s1 - sb);
-            // segment bounds of batch 0, loaded before sigma (loads complete in order)
-            const int64_t seg_i = seg0 + (int64_t)i * nb;
-            const int64_t p0 = uniform64(P.soff[seg_i]), p1 = uniform64(P.soff[seg_i + 1]);
-            const int64_t q0 = uniform64(P.sdoff[seg_i]), q1 = uniform64(P.sdoff[seg_i + 1]);
-            for (int e = tid; e < ns * NL; e += bd) {
-                const int sidx = e / NL, d = e - sidx * NL;
-                sigs[e] = A.sig[slot_base[d] + sb + sidx];
+        int nb = 1, NT = 0;
+        for (int i = 0;; ++i) {
+            const int sb = c_sb, ns = c_ns;
+            const int64_t p0 = uniform64(np0), p1 = uniform64(np1), q0 = uniform64(nq0), q1 = uniform64(nq1);
+#pragma unroll
+            for (int k = 0; k < NSIG; ++k) {
+                const int e = tid + k * TPB;
+                if (e < ns * NL) sigs[par][e] = sreg[k];
             }
+            __syncthreads();                          // sigma and the record visible; psi free
+            const int s1 = uniform(rec[1]);
+            NT = uniform(rcum[5]);
+            nb = (NT + kPairTB - 1) / kPairTB;
+            const bool last = sb + ns >= s1;
+            int64_t nseg;
+            if (!last) {
+                c_sb = sb + kFastSrc;
+                c_ns = min(kFastSrc, s1 - c_sb);
+                nseg = seg0 + (int64_t)(i + 1) * nb;
+            } else {
+                c_sb = next_s0;
+                c_ns = more ? min(kFastSrc, next_s1 - next_s0) : 0;
+                nseg = next_seg0;
+            }
+            prefetch(c_sb, c_ns, nseg);
+            if (p0 + (int64_t)wave * 128 < p1) fetch(p0 + (int64_t)wave * 128, p1);   // first pair block of batch 0
             {
-                // psi = C sigma: the same FP64 MFMA tiling as k_local_fast
-                __syncthreads();
-                if (p0 + (int64_t)wave * 128 < p1) fetch(p0 + (int64_t)wave * 128, p1);   // first pair block of batch 0
+                // psi = C sigma
                 mfma_d4 acc[kPairRB];
 #pragma unroll
-                for (int j = 0; j < kPairRB; ++j) acc[j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+                for (int r = 0; r < kPairRB; ++r) acc[r] = mfma_d4{0.0, 0.0, 0.0, 0.0};
                 const int q = lane & 15;
 #pragma unroll
-                for (int j = 0; j < kPairRB; ++j) {
-                    const int rb = wave + j * nwave;
+                for (int r = 0; r < kPairRB; ++r) {
+                    const int rb = wave + r * nwave;
                     if (rb >= nblk) continue;              // uniform across the wave
 #pragma unroll
                     for (int ks = 0; ks < KS; ++ks) {
                         const int d = 4 * ks + (lane >> 4);
-                        const double b = (q < ns && d < NL) ? sigs[q * NL + d] : 0.0;
-                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[j][ks], b, acc[j], 0, 0, 0);
+                        const double b = (q < ns && d < NL) ? sigs[par][q * NL + d] : 0.0;   // B[d][q] = sigma_{q,d}
+                        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[r][ks], b, acc[r], 0, 0, 0);
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < kPairRB; ++j) {
-                    const int rb = wave + j * nwave;
+                for (int r = 0; r < kPairRB; ++r) {
+                    const int rb = wave + r * nwave;
                     if (rb >= nblk || q >= ns) continue;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = rb * 16 + (lane >> 4) + 4 * r;
-                        if (row < nrow) psi[q * psiSrc + (row / D) * kRow + row % D] = acc[j][r];
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = rb * 16 + (lane >> 4) + 4 * e;   // D[lane][e] = C[lane/16 + 4 e][lane%16]
+                        if (row < nrow) psi[q * psiSrc + (row / D) * kRow + row % D] = acc[r][e];
                     }
                 }
             }
-            __syncthreads();
+            __syncthreads();                          // psi visible
             for (int b = 0; b < nb; ++b) {
-                const int tb0 = b * kPairTB, ntb = min(kPairTB, NT - tb0);
-                if (nb > 1) {
-                    for (int t = tid; t < ntb; t += bd) tacc[t] = 0.0;
-                    __syncthreads();
-                }
-                const int64_t seg = seg_i + b;
+                const int64_t seg = seg0 + (int64_t)i * nb + b;
                 const int64_t bp0 = b ? uniform64(P.soff[seg]) : p0, bp1 = b ? uniform64(P.soff[seg + 1]) : p1;
                 const int64_t stride = (int64_t)nwave * 128;
                 int64_t base = bp0 + (int64_t)wave * 128;
-                // the next block's words and coordinates are loaded while this block is evaluated
-                // (batch 0's first block was loaded before the profile synthesis)
                 if (b && base < bp1) fetch(base, bp1);
                 for (; base < bp1; base += stride) {
                     const uint32_t w0 = nw0, w1 = nw1;
@@ -1455,8 +1495,8 @@ __global__ __launch_bounds__(TPB, 1024 / TPB) void k_local_pairs(LocalArgs A, Pa
                     double u0, u1;
                     cheb_eval2n<D>(psi + (int)((w0 >> 16) & 15u) * psiSrc + (int)(w0 >> 20) * kRow, x0,
                                    psi + (int)((w1 >> 16) & 15u) * psiSrc + (int)(w1 >> 20) * kRow, x1, u0, u1);
-                    // padding lanes add 0 to distinct sums (no same-address atomics, no branch around
-                    // the two sums, which would then be evaluated one after the other)
+                    // padding lanes add 0 to distinct sums (no same-address atomics, and no branch
+                    // around the two sums, which would then be evaluated one after the other)
                     atomicAdd(&tacc[v0 ? (int)(w0 & 0xffffu) : lane], v0 ? u0 : 0.0);
                     atomicAdd(&tacc[v1 ? (int)(w1 & 0xffffu) : 64 + lane], v1 ? u1 : 0.0);
                 }
@@ -1465,19 +1505,35 @@ __global__ __launch_bounds__(TPB, 1024 / TPB) void k_local_pairs(LocalArgs A, Pa
                 for (int64_t q = bq0 + (int64_t)wave * 64 + lane; q < bq1; q += (int64_t)nwave * 64) {
                     const uint32_t wq = P.dent[q];
                     const double *__restrict__ wd = P.dw + q * NL;
-                    const double *sg = sigs + (int)((wq >> 16) & 15u) * NL;
+                    const double *sg = sigs[par] + (int)((wq >> 16) & 15u) * NL;
                     double v = 0.0;
 #pragma unroll 5
                     for (int d = 0; d < NL; ++d) v = fma(wd[d], sg[d], v);
                     atomicAdd(&tacc[wq & 0xffffu], v);
                 }
-                __syncthreads();
-                if (nb > 1 || i == nch - 1) {
-                    for (int t = tid; t < ntb; t += bd) {
+                if (nb > 1) {                         // several target batches: flush each
+                    const int tb0 = b * kPairTB, ntb = min(kPairTB, NT - tb0);
+                    __syncthreads();
+                    for (int t = tid; t < ntb; t += TPB) {
                         const double v = tacc[t];
-                        if (v != 0.0) unsafeAtomicAdd(&A.ul[block_target(rbeg, rcum, tb0 + t)], v);
+                        if (v != 0.0) {
+                            unsafeAtomicAdd(&A.ul[block_target(rbeg, rcum, tb0 + t)], v);
+                            tacc[t] = 0.0;
+                        }
                     }
                     __syncthreads();
+                }
+            }
+            par ^= 1;
+            if (last) break;
+        }
+        if (nb == 1) {                                // one batch: the sums of the whole cell
+            __syncthreads();
+            for (int t = tid; t < NT; t += TPB) {
+                const double v = tacc[t];
+                if (v != 0.0) {
+                    unsafeAtomicAdd(&A.ul[block_target(rbeg, rcum, t)], v);
+                    tacc[t] = 0.0;
                 }
             }
         }
