@@ -110,3 +110,29 @@ def test_pair_lists_dyadic_pairs_against_oracle(precision):
     err = rel_l2(U, Uo)
     print(f"near-coincident {precision}: rel L2 vs oracle {err:.3e}")
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pair_lists_several_target_batches(precision):
+    """4096 sources = targets clustered in a 0.2 x 0.2 square: one cell's 5 x 5 block holds
+    all 4096 targets, more than one batch of 1024, so each chunk's pairs come in four
+    segments flushed one after the other.  Against the per-step search (which batches
+    512 targets at a time) and the oracle."""
+    from wfp_workloads import family_g_workload
+    rng = np.random.default_rng(41)
+    src = np.array([0.3, -0.2]) + rng.uniform(-0.1, 0.1, size=(4096, 2))
+    w = family_g_workload("cluster4096", rng, src, L=4.0, nt=40)
+    steps = {20, 40}
+    ia, ib, ua, ub = _lockstep(w, precision, steps)
+    assert ia["local_path"] == 2
+    for m in sorted(steps):
+        assert np.isfinite(ua[m]).all() and np.linalg.norm(ub[m]) > 0
+        d = rel_l2(ua[m], ub[m])
+        print(f"cluster {precision} step {m}: pair lists vs search rel diff {d:.2e}")
+        assert d <= _agreement(ia, ib, w)
+    tg = np.sort(rng.choice(w.Nx, size=24, replace=False))
+    U = np.array([ua[m][tg] for m in sorted(steps)]).T
+    Uo = oracle_field(w, ia, tg, sorted(steps))
+    err = rel_l2(U, Uo)
+    print(f"cluster {precision}: rel L2 vs oracle {err:.3e}")
+    assert err <= 1e-6

@@ -170,3 +170,56 @@ def test_config4_full_size_sampled():
     err = rel_l2(U, Uo)
     print(f"config4 mixed: rel L2 {err:.3e} over {U.size} samples (oracle {time.time() - t0:.1f} s)")
     assert err <= TOL_E2E
+
+
+def _curve_case(idx, precision, steps, n_near, n_any, seed):
+    """Step config idx (a curve of sources, 900 x 900 target mesh) to max(steps) and compare
+    seeded targets (n_near with a source within delta, n_any anywhere) with the oracle."""
+    import time
+    import torch
+    from scipy.spatial import cKDTree
+    import paper_2604_07170_amd as pa
+    from wfp_workloads import config
+    w = config(idx)
+    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=precision, interp_order=w.p)
+    info = plan.info()
+    assert info["local_path"] == 2 and min(steps) > info["LA"] + info["W"]
+    rng = np.random.default_rng(seed)
+    dist, _ = cKDTree(w.src).query(w.tgt, k=1)
+    near = np.flatnonzero(dist < info["delta"])
+    tg = np.sort(np.concatenate([rng.choice(near, size=n_near, replace=False),
+                                 rng.choice(w.Nx, size=n_any, replace=False)]))
+    L = info["lookahead"]
+    dev = torch.device("cuda", 0)
+    params = w.torch_params(dev)
+    u = torch.empty(w.Nx, dtype=torch.float64, device=dev)
+    tgd = torch.as_tensor(tg, device=dev)
+    got = {}
+    t0 = time.time()
+    for n in range(1, max(steps) + L + 1):
+        plan.step(w.sigma_torch(n * w.dt, dev, params))
+        if n - L in steps:
+            plan.evaluate(u)
+            got[n - L] = u[tgd].cpu().numpy()
+    torch.cuda.synchronize()
+    t_gpu = time.time() - t0
+    U = np.array([got[s] for s in steps]).T
+    t0 = time.time()
+    Uo = oracle_field(w, info, tg, steps, self_mode=0)
+    err = rel_l2(U, Uo)
+    print(f"{w.name} {precision}: rel L2 {err:.3e} over {U.size} samples ({len(near)} of {w.Nx} targets within "
+          f"delta of a source; {max(steps) + L} steps in {t_gpu:.1f} s, oracle {time.time() - t0:.1f} s)")
+    return err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config5_circle_grid_targets(precision):
+    """Sec. 5.3: 10^5 sources on a circle that touches the edge of B, frequencies and onsets
+    rising along it, 900 x 900 target mesh; 8 targets x 2 steps after the far-history onset."""
+    assert _curve_case(5, precision, [4400, 5000], n_near=6, n_any=2, seed=15) <= TOL_E2E
+
+
+def test_config6_wiggly_curve_grid_targets():
+    """Sec. 5.4: 10^6 sources on the oscillating curve, 900 x 900 target mesh; 2 targets x
+    2 steps after the far-history onset, in the benchmark's precision."""
+    assert _curve_case(6, "mixed", [4400, 5000], n_near=1, n_any=1, seed=16) <= TOL_E2E

@@ -136,6 +136,29 @@ def star_curve(M: int, r0: float = 1.0, amp: float = 0.3, lobes: int = 5,
     return np.stack([scale * r * np.cos(th), scale * r * np.sin(th)], axis=1)
 
 
+def grid_targets(n: int = 900) -> np.ndarray:
+    """A regular n x n mesh of targets over B (cell centres, row-major in y then x)."""
+    c = -1.0 + (2.0 * np.arange(n) + 1.0) / n
+    X, Y = np.meshgrid(c, c)
+    return np.stack([X.ravel(), Y.ravel()], 1)
+
+
+def circle_sources(M: int) -> np.ndarray:
+    """M points equispaced in s on [0.8 cos s + 0.2, 0.8 sin s + 0.2] (touches the edge of B)."""
+    s = 2.0 * np.pi * np.arange(M) / M
+    return np.clip(np.stack([0.8 * np.cos(s) + 0.2, 0.8 * np.sin(s) + 0.2], 1), -1.0, 1.0)
+
+
+def wiggly_sources(M: int) -> np.ndarray:
+    """M points equispaced in s on r(s) = 0.61 + 0.2 cos 60s - 0.1 sin 20s + 0.05 cos 30s - 0.1 cos 40s.
+
+    The curve reaches |x| = 1.0029 near s = 0 and s = pi; those points are clipped onto the
+    edge of B (the library takes points in [-1, 1]^2)."""
+    s = 2.0 * np.pi * np.arange(M) / M
+    r = 0.61 + 0.2 * np.cos(60 * s) - 0.1 * np.sin(20 * s) + 0.05 * np.cos(30 * s) - 0.1 * np.cos(40 * s)
+    return np.clip(np.stack([r * np.cos(s), r * np.sin(s)], 1), -1.0, 1.0)
+
+
 def displaced(rng, pts: np.ndarray, frac: float = 0.3) -> np.ndarray:
     """Targets = points moved by a seeded offset of about frac x mean spacing."""
     M = pts.shape[0]
@@ -227,6 +250,19 @@ def config(idx: int, displaced_targets: bool = False) -> Workload:
         src = uniform_square(rng, 1_000_000)
         w = family_e_workload("cfg4_M1e6_300wl_E", rng, src, L=300.0, nt=6000, dt=8.0 / 7150.0,
                               T_ref=8.0 / 7150.0 * 6000)
+    elif idx in (5, 6):
+        # the curve examples of Sec. 5: the Sec. 5.2 step, window and final time T = 8, a
+        # 900 x 900 target mesh (no target on a source), t0 rising from 1.5 to 7 along the
+        # curve; on the circle omega rises linearly to 300 pi along it, on the wiggly curve
+        # omega = 300 pi z^(1/3) with z uniform
+        M = 100_000 if idx == 5 else 1_000_000
+        src = circle_sources(M) if idx == 5 else wiggly_sources(M)
+        name = "cfg5_circle_M1e5_grid900" if idx == 5 else "cfg6_wiggly_M1e6_grid900"
+        w = family_e_workload(name, rng, src, L=300.0, nt=7150, dt=8.0 / 7150.0, T_ref=8.0, tgt=grid_targets(900))
+        frac = np.arange(M) / M
+        w.t0 = 1.5 + 5.5 * frac
+        if idx == 5:
+            w.omega = 300.0 * np.pi * frac
     else:
         raise ValueError(f"no such configuration {idx}")
     if displaced_targets:
