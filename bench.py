@@ -235,8 +235,9 @@ def main():
     plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=args.precision, interp_order=w.p,
                     max_steps=args.warmup + args.steps + 32)
     info = plan.info()
+    init_s = time.time() - t0
     L = info["lookahead"]
-    log(f"[bench] {w.name}: plan ready in {time.time() - t0:.1f}s  modes={info['n_modes']} nf={info['nf']} "
+    log(f"[bench] {w.name}: plan ready in {init_s:.1f}s  modes={info['n_modes']} nf={info['nf']} "
         f"band={info['band']} pairs={info['n_local_pairs']} lookahead={L} HBM={info['bytes_device'] / 2**30:.1f}GiB")
     params = w.torch_params(dev)
     u = torch.empty(w.Nx, dtype=torch.float64, device=dev)
@@ -361,6 +362,7 @@ def main():
         "roofline": roof,
         "hbm_roofline_step_frac": round(step_hbm_frac, 4),
         "hbm_copy_GBs": round(copy_gbs, 1),
+        "plan_init_s": round(init_s, 2),
         "stages": per_stage,
         "cpu_baseline": cpu,
         "sample_rel_err_vs_oracle": sample_err,
