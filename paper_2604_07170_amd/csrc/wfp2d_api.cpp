@@ -235,7 +235,7 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
         doff[s + 1] = doff[s] + dcnt[s];
     }
     const int64_t npair = off.back(), ndy = doff.back();
-    const int64_t bytes = npair * (int64_t)(sizeof(uint32_t) + sizeof(double)) +
+    const int64_t bytes = npair * (int64_t)sizeof(uint64_t) +
                           ndy * (int64_t)(sizeof(uint32_t) + p.g.nlev * sizeof(double)) +
                           2 * (nslot + 1 + nslot / kFastSrc + 1) * (int64_t)sizeof(int64_t);
     size_t free_b = 0, total_b = 0;
@@ -264,8 +264,7 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
         upload(p.d_seg_off, so);
         upload(p.d_seg_doff, sdo);
     }
-    p.d_pair_ent = p.alloc<uint32_t>(npair);
-    p.d_pair_x = p.alloc<double>(npair);
+    p.d_pair_pw = p.alloc<uint64_t>(npair);
     p.d_pair_dent = p.alloc<uint32_t>(ndy);
     p.d_pair_dw = p.alloc<double>(ndy * p.g.nlev);
     hip_check(launch_pairs_build(p, true, nullptr, nullptr), "pair fill");

@@ -179,8 +179,8 @@ struct Plan {
     int64_t *d_seg_off = nullptr, *d_seg_doff = nullptr;     // first pair of each segment, [n_seg + 1]
     double *d_pair_dw = nullptr;      // eta_d(r) of each pair with r < dt/2, [n_dy_pairs][nlev]
     int32_t n_cu = 256;               // compute units of the device (persistent grids)
-    uint32_t *d_pair_ent = nullptr, *d_pair_dent = nullptr;
-    double *d_pair_x = nullptr;
+    uint64_t *d_pair_pw = nullptr;    // regular pairs, one packed word each
+    uint32_t *d_pair_dent = nullptr;
 
     std::string err;
 

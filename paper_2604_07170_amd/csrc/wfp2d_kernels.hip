@@ -1210,17 +1210,32 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
 // k_pairs_build finds them with the cell blocks of k_local_fast (a count pass,
 // then a fill pass at offsets scanned on the host) and stores them per segment
 // (a chunk of kFastSrc sources of one cell x a batch of kPairTB targets of the
-// cell's 5 x 5 block): for a pair with r >= dt/2 the word t | s << 16 | k << 20
-// (t: target in the batch, s: source in the chunk) and x in FP64; for a pair
-// with r < dt/2 (dyadic sub-panels) the word t | s << 16 and r.  Within a
-// segment the pairs are ordered by source, then by target.
+// cell's 5 x 5 block): for a pair with r >= dt/2 one 64-bit word (pair_pack:
+// target in the batch, source in the chunk, panel k, Chebyshev coordinate x);
+// for a pair with r < dt/2 (dyadic sub-panels) the word t | s << 16 and its
+// weights eta_d(r).  Within a segment the pairs are ordered by source, then by
+// target.
 // k_local_pairs then does, per step and chunk: the profile coefficients
 // psi = C sigma with FP64 MFMA (as k_local_fast), then its waves take 128-pair
 // blocks of the segment in turn, two interleaved Clenshaw sums per lane, with
 // per-target sums in LDS; there is no candidate test, compaction or square
 // root per pair, and every wave gets the same number of pairs.
 // ---------------------------------------------------------------------------
-static_assert(kFastSrc <= 16 && kPairTB <= 65536, "pair words hold the source in 4 bits and the target in 16");
+static_assert(kFastSrc <= 16 && kPairTB <= 1024, "pair words hold the target in 10 bits and the source in 4");
+
+// A regular pair in one 64-bit word: target in batch (bits 0-9), source in chunk
+// (10-13), panel (14-19), and the Chebyshev coordinate x in [-1, 1] as a 44-bit
+// fixed-point fraction (20-63; resolution 1.1e-13).
+constexpr double kPairXScale = 2.0 / 17592186044415.0;   // 2 / (2^44 - 1)
+__device__ __forceinline__ uint64_t pair_pack(int t, int s, int k, double x)
+{
+    const uint64_t q = (uint64_t)llrint((fmin(1.0, fmax(-1.0, x)) + 1.0) / kPairXScale);
+    return (uint64_t)t | ((uint64_t)s << 10) | ((uint64_t)k << 14) | (q << 20);
+}
+__device__ __forceinline__ int pair_t(uint64_t w) { return (int)(w & 1023u); }
+__device__ __forceinline__ int pair_s(uint64_t w) { return (int)((w >> 10) & 15u); }
+__device__ __forceinline__ int pair_k(uint64_t w) { return (int)((w >> 14) & 63u); }
+__device__ __forceinline__ double pair_x(uint64_t w) { return fma((double)(w >> 20), kPairXScale, -1.0); }
 
 // Work cells (cells with sources and with targets in their block), one record
 // of kCellRec int32 each: the cell's sources [s0, s1) in sorted order, then the
@@ -1233,16 +1248,16 @@ struct PairLists {
     int n_work;
     const int64_t *off, *doff;    // first pair of each (segment, source in chunk), [n_seg * kFastSrc + 1]
     const int64_t *soff, *sdoff;  // first pair of each segment, [n_seg + 1]
-    const uint32_t *ent;          // regular pairs: t | s << 16 | k << 20
-    const double *x;              //   and their Chebyshev coordinates
+    const uint64_t *pw;           // regular pairs (pair_pack)
     const uint32_t *dent;         // pairs with r < dt/2: t | s << 16
     const double *dw;             //   and their weights eta_d(r), d < nlev (dyadic sub-panel tables)
 };
 
 struct PairBuild {
     int64_t *cnt, *dcnt;          // count pass: pairs per (segment, source in chunk)
-    uint32_t *ent, *dent;         // fill pass: the lists, at the offsets of PairLists
-    double *x, *dw;
+    uint64_t *pw;                 // fill pass: the lists, at the offsets of PairLists
+    uint32_t *dent;
+    double *dw;
     int fill, nlev;
 };
 
@@ -1298,8 +1313,7 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
                         const int64_t e = o_reg + c_reg + __popcll(mr & below);
                         double x;
                         const int k = fast_panel(A, sqrt(r2), W, dt, x);
-                        B.ent[e] = (uint32_t)t | ((uint32_t)sl << 16) | ((uint32_t)k << 20);
-                        B.x[e] = x;
+                        B.pw[e] = pair_pack(t, sl, k, x);
                     }
                     if (B.fill && dya) {
                         const int64_t e = o_dy + c_dy + __popcll(md & below);
@@ -1404,14 +1418,11 @@ __global__ __launch_bounds__(TPB, 4) void k_local_pairs(LocalArgs A, PairLists P
     int par = 0;
 
     // pair words and coordinates of a wave's next 128-pair block (loaded ahead of use)
-    uint32_t nw0 = 0u, nw1 = 0u;
-    double nx0 = 0.0, nx1 = 0.0;
+    uint64_t nw0 = 0u, nw1 = 0u;
     auto fetch = [&](int64_t bs, int64_t pend) {
         const int64_t e0 = bs + lane, e1 = e0 + 64;
-        nw0 = e0 < pend ? P.ent[e0] : 0u;
-        nx0 = e0 < pend ? P.x[e0] : 0.0;
-        nw1 = e1 < pend ? P.ent[e1] : 0u;
-        nx1 = e1 < pend ? P.x[e1] : 0.0;
+        nw0 = e0 < pend ? P.pw[e0] : 0u;
+        nw1 = e1 < pend ? P.pw[e1] : 0u;
     };
 
     for (int j = 0; wk < P.n_work; ++j, wk += G) {
@@ -1488,17 +1499,16 @@ __global__ __launch_bounds__(TPB, 4) void k_local_pairs(LocalArgs A, PairLists P
                 int64_t base = bp0 + (int64_t)wave * 128;
                 if (b && base < bp1) fetch(base, bp1);
                 for (; base < bp1; base += stride) {
-                    const uint32_t w0 = nw0, w1 = nw1;
-                    const double x0 = nx0, x1 = nx1;
+                    const uint64_t w0 = nw0, w1 = nw1;
                     const bool v0 = base + lane < bp1, v1 = base + 64 + lane < bp1;
                     if (base + stride < bp1) fetch(base + stride, bp1);
                     double u0, u1;
-                    cheb_eval2n<D>(psi + (int)((w0 >> 16) & 15u) * psiSrc + (int)(w0 >> 20) * kRow, x0,
-                                   psi + (int)((w1 >> 16) & 15u) * psiSrc + (int)(w1 >> 20) * kRow, x1, u0, u1);
+                    cheb_eval2n<D>(psi + pair_s(w0) * psiSrc + pair_k(w0) * kRow, pair_x(w0),
+                                   psi + pair_s(w1) * psiSrc + pair_k(w1) * kRow, pair_x(w1), u0, u1);
                     // padding lanes add 0 to distinct sums (no same-address atomics, and no branch
                     // around the two sums, which would then be evaluated one after the other)
-                    atomicAdd(&tacc[v0 ? (int)(w0 & 0xffffu) : lane], v0 ? u0 : 0.0);
-                    atomicAdd(&tacc[v1 ? (int)(w1 & 0xffffu) : 64 + lane], v1 ? u1 : 0.0);
+                    atomicAdd(&tacc[v0 ? pair_t(w0) : lane], v0 ? u0 : 0.0);
+                    atomicAdd(&tacc[v1 ? pair_t(w1) : 64 + lane], v1 ? u1 : 0.0);
                 }
                 // pairs with r < dt/2: one lane per pair, sum over levels with the stored weights
                 const int64_t bq0 = b ? uniform64(P.sdoff[seg]) : q0, bq1 = b ? uniform64(P.sdoff[seg + 1]) : q1;
@@ -1827,8 +1837,7 @@ static PairLists pair_lists(const Plan &p)
     P.doff = p.d_pair_doff;
     P.soff = p.d_seg_off;
     P.sdoff = p.d_seg_doff;
-    P.ent = p.d_pair_ent;
-    P.x = p.d_pair_x;
+    P.pw = p.d_pair_pw;
     P.dent = p.d_pair_dent;
     P.dw = p.d_pair_dw;
     return P;
@@ -1841,8 +1850,7 @@ hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt)
     PairBuild B;
     B.cnt = cnt;
     B.dcnt = dcnt;
-    B.ent = p.d_pair_ent;
-    B.x = p.d_pair_x;
+    B.pw = p.d_pair_pw;
     B.dent = p.d_pair_dent;
     B.dw = p.d_pair_dw;
     B.fill = fill ? 1 : 0;
