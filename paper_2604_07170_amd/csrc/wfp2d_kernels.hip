@@ -257,27 +257,28 @@ template <class C> __device__ __forceinline__ void dft16(C *v, int sign)
     for (int i = 0; i < 16; ++i) v[i] = out[i];
 }
 
-// last Stockham pass of radix R in {2, 4, 8}: each thread does 16/R butterflies
+// last Stockham pass of radix R in {2, 4, 8}: each thread does 16/R butterflies.
+// Q and Ns = 2^lns are powers of two: index arithmetic by shifts and masks.
 template <int R, class C>
-__device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int Ns, int sign, const double2 *tw, int P)
+__device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int lns, int sign, const double2 *tw, int P)
 {
-    constexpr int nb = 16 / R;
-    const int tid = threadIdx.x, T = Q >> 4, QR = Q / R;
+    constexpr int nb = 16 / R, lR = R == 2 ? 1 : R == 4 ? 2 : 3;
+    const int tid = threadIdx.x, T = Q >> 4, QR = Q >> lR, Ns = 1 << lns;
 #pragma unroll
     for (int i = 0; i < nb; ++i)
 #pragma unroll
         for (int r = 0; r < R; ++r) v[i * R + r] = lds[lpad(tid + T * i + r * QR)];
     __syncthreads();
-    const int stride = (Q / (R * Ns)) * P;
+    const int stride = (Q >> (lR + lns)) * P;
 #pragma unroll
     for (int i = 0; i < nb; ++i) {
-        const int j = tid + T * i, k = j % Ns;
+        const int j = tid + T * i, k = j & (Ns - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], twid<C>(tw, k * r * stride, sign));
         if (R == 2) dft2(v[i * R], v[i * R + 1]);
         else if (R == 4) dft4(v[i * R], v[i * R + 1], v[i * R + 2], v[i * R + 3], sign);
         else dft8(v + i * R, sign);
-        const int o = (j / Ns) * Ns * R + k;
+        const int o = ((j >> lns) << (lns + lR)) + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[lpad(o + r * Ns)] = v[i * R + r];
     }
@@ -295,25 +296,25 @@ __device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const double2 *tw
 #pragma unroll
     for (int r = 0; r < 16; ++r) lds[lpad(tid * 16 + r)] = v[r];
     __syncthreads();
-    int Ns = 16, Lleft = L - 4;
+    int lns = 4, Lleft = L - 4;                     // Ns = 2^lns
     while (Lleft >= 4) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = lds[lpad(tid + r * T)];
         __syncthreads();
-        const int k = tid % Ns, stride = (Q / (16 * Ns)) * P;
+        const int Ns = 1 << lns, k = tid & (Ns - 1), stride = (Q >> (4 + lns)) * P;
 #pragma unroll
         for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twid<C>(tw, k * r * stride, sign));
         dft16(v, sign);
-        const int o = (tid / Ns) * Ns * 16 + k;
+        const int o = ((tid >> lns) << (lns + 4)) + k;
 #pragma unroll
         for (int r = 0; r < 16; ++r) lds[lpad(o + r * Ns)] = v[r];
         __syncthreads();
-        Ns <<= 4;
+        lns += 4;
         Lleft -= 4;
     }
-    if (Lleft == 1) tail_pass<2>(lds, v, Q, Ns, sign, tw, P);
-    else if (Lleft == 2) tail_pass<4>(lds, v, Q, Ns, sign, tw, P);
-    else if (Lleft == 3) tail_pass<8>(lds, v, Q, Ns, sign, tw, P);
+    if (Lleft == 1) tail_pass<2>(lds, v, Q, lns, sign, tw, P);
+    else if (Lleft == 2) tail_pass<4>(lds, v, Q, lns, sign, tw, P);
+    else if (Lleft == 3) tail_pass<8>(lds, v, Q, lns, sign, tw, P);
 }
 
 // map sub-transform output k' of branch s to a signed mode n in [-R, R]; false if unused
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
 //   MODE 1 (rows): X(k) = T2t[line][k] for k <= R; output Re y -> cgrid[line][m].
 // ---------------------------------------------------------------------------
 template <class R, int MODE>
-__global__ __launch_bounds__(512) void k_fft_t2(const typename cplx<R>::T *__restrict__ in, void *__restrict__ outv, const int32_t *__restrict__ col_off,
+__global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t2(const typename cplx<R>::T *__restrict__ in, void *__restrict__ outv, const int32_t *__restrict__ col_off,
                          const int32_t *__restrict__ col_ny0, const typename cplx<R>::T *__restrict__ corr,
                          const double2 *__restrict__ tw, Geom g)
 {
