@@ -448,6 +448,16 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         for (int t = 0; t < ntile; ++t) off[t + 1] += off[t];
         std::vector<int32_t> pos(off.begin(), off.end() - 1);
         for (int64_t i = 0; i < Nx; ++i) lst[pos[(tbase[i].y / kTile) * g.ntx + tbase[i].x / kTile]++] = (int32_t)i;
+        // origins and weights in this processing order, so that the interpolation kernel
+        // reads them without waiting for the target index
+        std::vector<int2> tb(Nx);
+        std::vector<double> tw(twts.size());
+        for (int64_t e = 0; e < Nx; ++e) {
+            tb[e] = tbase[lst[e]];
+            std::copy(twts.begin() + (size_t)lst[e] * 2 * w, twts.begin() + (size_t)(lst[e] + 1) * 2 * w, tw.begin() + (size_t)e * 2 * w);
+        }
+        tbase.swap(tb);
+        twts.swap(tw);
         p.d_ttile_off = p.alloc<int32_t>(ntile + 1);
         upload(p.d_ttile_off, off);
         p.d_ttile_tgt = p.alloc<int32_t>(Nx);

@@ -151,7 +151,8 @@ struct Plan {
     void *d_T2 = nullptr;             // [R+1][Lpad] complex Real
     void *d_T2t = nullptr;            // [Lpad][R+1] its transpose
     void *d_cgrid = nullptr;          // [Lpad][Lpad] Real
-    int2 *d_tgt_base = nullptr;
+    int2 *d_tgt_base = nullptr;       // interpolation origin and weights of each target, in the
+                                      // processing order d_ttile_tgt (not sorted order)
     void *d_tgt_wts = nullptr;
     int32_t *d_ttile_off = nullptr, *d_ttile_tgt = nullptr;
     double *d_uh = nullptr, *d_ul = nullptr;   // sorted target order

@@ -683,9 +683,9 @@ __global__ __launch_bounds__(256) void k_interp(const R *__restrict__ cgrid, con
     double part = 0.0;
     int i = 0;
     if (e < Nx) {
-        i = tlist[e];
-        const int2 b = base[i];
-        const R *__restrict__ wi = wts + (size_t)i * 2 * w;
+        i = tlist[e];                                 // output slot (sorted target order)
+        const int2 b = base[e];                       // origins and weights are stored in processing order
+        const R *__restrict__ wi = wts + (size_t)e * 2 * w;
         for (int bb = r; bb < w; bb += 8) {
             const R *__restrict__ row = cgrid + (size_t)(b.y + bb) * Lpad + b.x;
             double s = 0.0;
