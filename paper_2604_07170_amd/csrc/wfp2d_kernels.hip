@@ -259,15 +259,25 @@ template <class C> __device__ __forceinline__ void dft16(C *v, int sign)
 
 // last Stockham pass of radix R in {2, 4, 8}: each thread does 16/R butterflies.
 // Q and Ns = 2^lns are powers of two: index arithmetic by shifts and masks.
+// LDS index of line element i: padded by one slot every 16 (against bank conflicts)
+// when Q >= 256, unpadded below.  Every stride the passes use is then either a multiple
+// of 16 (padded case) or unpadded, so the index of a + r S is idx(a) + r S' with
+// S' = S + S/16 (padded) or S: a base plus uniform multiples, no per-element arithmetic.
+__device__ __forceinline__ int fidx(int i, bool pad) { return pad ? lpad(i) : i; }
+__device__ __forceinline__ int fstr(int s, bool pad) { return pad ? s + (s >> 4) : s; }
+
+// last Stockham pass of radix R in {2, 4, 8}: each thread does 16/R butterflies.
+// Q and Ns = 2^lns are powers of two: index arithmetic by shifts and masks.
 template <int R, class C>
-__device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int lns, int sign, const double2 *tw, int P)
+__device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int lns, int sign, const double2 *tw, int P, bool pad)
 {
     constexpr int nb = 16 / R, lR = R == 2 ? 1 : R == 4 ? 2 : 3;
     const int tid = threadIdx.x, T = Q >> 4, QR = Q >> lR, Ns = 1 << lns;
+    const int rb = fidx(tid, pad), Tp = fstr(T, pad), QRp = fstr(QR, pad), Nsp = fstr(Ns, pad);
 #pragma unroll
     for (int i = 0; i < nb; ++i)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[i * R + r] = lds[lpad(tid + T * i + r * QR)];
+        for (int r = 0; r < R; ++r) v[i * R + r] = lds[rb + i * Tp + r * QRp];
     __syncthreads();
     const int stride = (Q >> (lR + lns)) * P;
 #pragma unroll
@@ -278,43 +288,45 @@ __device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int lns, int sign
         if (R == 2) dft2(v[i * R], v[i * R + 1]);
         else if (R == 4) dft4(v[i * R], v[i * R + 1], v[i * R + 2], v[i * R + 3], sign);
         else dft8(v + i * R, sign);
-        const int o = ((j >> lns) << (lns + lR)) + k;
+        const int ob = fidx(((j >> lns) << (lns + lR)) + k, pad);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lpad(o + r * Ns)] = v[i * R + r];
+        for (int r = 0; r < R; ++r) lds[ob + r * Nsp] = v[i * R + r];
     }
     __syncthreads();
 }
 
 // One workgroup transforms one line.  v[r] (r < 16) holds x[tid + r Q/16] on
-// entry; the result is left in lds (natural order, padded index).
+// entry; the result is left in lds (natural order, index fidx).
 template <class C>
 __device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const double2 *tw, int P)
 {
-    const int tid = threadIdx.x, T = Q >> 4;
-    // first radix-16 pass (Ns = 1): no twiddles
+    const bool pad = Q >= 256;
+    const int tid = threadIdx.x, T = Q >> 4, Tp = fstr(T, pad), rb = fidx(tid, pad);
+    // first radix-16 pass (Ns = 1): no twiddles; idx(16 tid + r) = idx(16 tid) + r
     dft16(v, sign);
+    const int b1 = pad ? tid * 17 : tid * 16;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[lpad(tid * 16 + r)] = v[r];
+    for (int r = 0; r < 16; ++r) lds[b1 + r] = v[r];
     __syncthreads();
     int lns = 4, Lleft = L - 4;                     // Ns = 2^lns
     while (Lleft >= 4) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = lds[lpad(tid + r * T)];
+        for (int r = 0; r < 16; ++r) v[r] = lds[rb + r * Tp];
         __syncthreads();
-        const int Ns = 1 << lns, k = tid & (Ns - 1), stride = (Q >> (4 + lns)) * P;
+        const int Ns = 1 << lns, k = tid & (Ns - 1), stride = (Q >> (4 + lns)) * P, Nsp = fstr(Ns, pad);
 #pragma unroll
         for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twid<C>(tw, k * r * stride, sign));
         dft16(v, sign);
-        const int o = ((tid >> lns) << (lns + 4)) + k;
+        const int ob = fidx(((tid >> lns) << (lns + 4)) + k, pad);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) lds[lpad(o + r * Ns)] = v[r];
+        for (int r = 0; r < 16; ++r) lds[ob + r * Nsp] = v[r];
         __syncthreads();
         lns += 4;
         Lleft -= 4;
     }
-    if (Lleft == 1) tail_pass<2>(lds, v, Q, lns, sign, tw, P);
-    else if (Lleft == 2) tail_pass<4>(lds, v, Q, lns, sign, tw, P);
-    else if (Lleft == 3) tail_pass<8>(lds, v, Q, lns, sign, tw, P);
+    if (Lleft == 1) tail_pass<2>(lds, v, Q, lns, sign, tw, P, pad);
+    else if (Lleft == 2) tail_pass<4>(lds, v, Q, lns, sign, tw, P, pad);
+    else if (Lleft == 3) tail_pass<8>(lds, v, Q, lns, sign, tw, P, pad);
 }
 
 // map sub-transform output k' of branch s to a signed mode n in [-R, R]; false if unused
@@ -371,7 +383,7 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int kk = tid + i * T;
-                const C y = lds[lpad(kk)];
+                const C y = lds[fidx(kk, g.Q >= 256)];
                 if (kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, tw_at<C>(tt, kk * s)));   // kk s < Q P
                 if (kk >= g.Q - g.R) {
                     const int n2 = kk - g.Q;
@@ -406,7 +418,7 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
                 int n;
                 if (!out_mode(kp, s, g, n)) continue;
                 if (MODE == 1 && (double)(nx * nx + n * n) > g.Rd2) continue;
-                out[(size_t)line * g.N + n + g.R] = cmul(lds[lpad(kp)], corr[n + g.R]);
+                out[(size_t)line * g.N + n + g.R] = cmul(lds[fidx(kp, g.Q >= 256)], corr[n + g.R]);
             }
             __syncthreads();
         }
@@ -467,7 +479,7 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t2(const ty
         for (int i = 0; i < 16; ++i) {
             const int m = tid + i * T;
             if (m < g.Lpad) {
-                C r2 = lds[lpad(m)];
+                C r2 = lds[fidx(m, g.Q >= 256)];
                 if (s > 0) r2 = cmul(r2, cconj(tw_at<C>(tt, s * m)));   // m < Lpad <= Q
                 acc[i] = cadd(acc[i], r2);
             }
