@@ -195,10 +195,14 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
     const int n = p.ncell;
     std::vector<int32_t> wrec;
     std::vector<int64_t> wseg(1, 0);
-    for (int c = 0; c < n * n; ++c) {
-        const int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+    // a work unit is kPairUnit adjacent cells of one row: their sources are contiguous in
+    // the sorted order, and the union of their 5 x 5 blocks (kPairUnit + 4 cells wide) holds
+    // every target within delta of any of them
+    for (int c = 0; c < n * n; c += (c % n + kPairUnit <= n - 1) ? kPairUnit : n - c % n) {
+        const int cx = c % n, cy = c / n, cx1 = std::min(n - 1, cx + kPairUnit - 1);
+        const int32_t s0 = cell_start[c], s1 = cell_start[(size_t)cy * n + cx1 + 1];
         if (s1 == s0) continue;
-        const int cx = c % n, cy = c / n, xa = std::max(0, cx - 2), xb = std::min(n - 1, cx + 2);
+        const int xa = std::max(0, cx - 2), xb = std::min(n - 1, cx1 + 2);
         int32_t rec[kPairRec] = {s0, s1};
         int32_t cum = 0;
         int r = 0;

@@ -28,6 +28,7 @@ constexpr int kFastSrc = 16;       // fast local kernel: sources per chunk
 constexpr int kFastRow = 512;      //   max coefficient rows (regular sub-panels x Chebyshev terms)
 constexpr int kPairTB = 1024;      // pair-list local kernel: targets per batch (LDS sums)
 constexpr int kPairRec = 16;       //   int32 per work-cell record
+constexpr int kPairUnit = 4;       //   adjacent cells of a row per work unit
 constexpr int kPairThreads = 1024; //   threads per workgroup: 16 waves, one workgroup per CU, or
 constexpr int kPairThreadsHalf = 512; //   8 waves, two per CU, when the rows fit 8 x kPairRB blocks
 constexpr int kPairRB = 2;         //   16-row blocks of the coefficient table per wave
