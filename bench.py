@@ -33,20 +33,29 @@ PEAK_FP64_TFLOPS = 78.6        # vector FP64
 PEAK_FP32_TFLOPS = 157.3       # vector FP32
 
 
+def kernels_digest() -> str:
+    """sha256 prefix of the kernels source with comments and blank lines removed (so that
+    only a change of code, not of its comments, invalidates the committed byte counters)."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_2604_07170_amd", "csrc", "wfp2d_kernels.hip")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    code = [re.sub(r"//.*$", "", l).rstrip() for l in src.splitlines()]
+    return hashlib.sha256("\n".join(l for l in code if l.strip()).encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` (read + written) from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, scaled by its copy-kernel calibration; None when the
-    summary is missing, does not list the kernel, or was taken on another kernels source."""
-    import hashlib
+    summary is missing, does not list the kernel, or was taken on other kernel code."""
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_cfg4_M1e6_mixed.md")
-    src = os.path.join(ROOT, "paper_2604_07170_amd", "csrc", "wfp2d_kernels.hip")
     try:
         text = open(path).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        digest = kernels_digest()
     except OSError:
         return None
-    m = re.search(r"sha256 prefix: ([0-9a-f]{16})", text)
+    m = re.search(r"code sha256 prefix: ([0-9a-f]{16})", text)
     if not m or m.group(1) != digest:
         return None
     for line in text.splitlines():

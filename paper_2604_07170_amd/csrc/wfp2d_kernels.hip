@@ -1220,10 +1220,12 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
 // Local part from pair lists made once per plan.  Sources and targets do not
 // move, so the set of pairs with 0 < r < delta, each pair's time-step panel k
 // and its Chebyshev coordinate x on that panel are the same at every step.
-// k_pairs_build finds them with the cell blocks of k_local_fast (a count pass,
-// then a fill pass at offsets scanned on the host) and stores them per segment
-// (a chunk of kFastSrc sources of one cell x a batch of kPairTB targets of the
-// cell's 5 x 5 block): for a pair with r >= dt/2 one 64-bit word (pair_pack:
+// k_pairs_build finds them per work unit (kPairUnit adjacent cells of a row,
+// whose sources are contiguous in the sorted order; its targets are the union
+// of their 5 x 5 cell blocks) with a count pass, then a fill pass at offsets
+// scanned on the host, and stores them per segment (a chunk of kFastSrc sources
+// of the unit x a batch of kPairTB of its targets): for a pair with r >= dt/2
+// one 64-bit word (pair_pack:
 // target in the batch, source in the chunk, panel k, Chebyshev coordinate x);
 // for a pair with r < dt/2 (dyadic sub-panels) the word t | s << 16 and its
 // weights eta_d(r).  Within a segment the pairs are ordered by source, then by
@@ -1250,14 +1252,14 @@ __device__ __forceinline__ int pair_s(uint64_t w) { return (int)((w >> 10) & 15u
 __device__ __forceinline__ int pair_k(uint64_t w) { return (int)((w >> 14) & 63u); }
 __device__ __forceinline__ double pair_x(uint64_t w) { return fma((double)(w >> 20), kPairXScale, -1.0); }
 
-// Work cells (cells with sources and with targets in their block), one record
-// of kCellRec int32 each: the cell's sources [s0, s1) in sorted order, then the
-// five runs of its 5 x 5 target block (rbeg[5], rcum[6]; see cell_block_runs).
+// Work units (units with sources and with targets in their block), one record
+// of kCellRec int32 each: the unit's sources [s0, s1) in sorted order, then the
+// five runs (block rows) of its targets (rbeg[5], rcum[6]; see block_target).
 constexpr int kCellRec = kPairRec;
 
 struct PairLists {
     const int32_t *wrec;          // [n_work][kCellRec]
-    const int64_t *wseg;          // first segment of each work cell, [n_work + 1]
+    const int64_t *wseg;          // first segment of each work unit, [n_work + 1]
     int n_work;
     const int64_t *off, *doff;    // first pair of each (segment, source in chunk), [n_seg * kFastSrc + 1]
     const int64_t *soff, *sdoff;  // first pair of each segment, [n_seg + 1]
@@ -1274,7 +1276,7 @@ struct PairBuild {
     int fill, nlev;
 };
 
-// targets of a cell's 5 x 5 block: five runs of the sorted target order (rows
+// targets of a work unit's block: five runs of the sorted target order (rows
 // cy-2..cy+2); run r starts at rbeg[r] and holds block positions [rcum[r], rcum[r+1])
 __device__ __forceinline__ int block_target(const int *rbeg, const int *rcum, int kk)
 {
