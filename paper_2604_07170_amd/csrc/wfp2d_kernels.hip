@@ -431,7 +431,11 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
 // m < Lpad, accumulated over the P branches.
 //   MODE 0 (columns): X from the packed half-disk coefficients of column n_x =
 //     line, times (2 or 1) conj(corr_x) conj(corr_y); output complex T2[line][m].
-//   MODE 1 (rows): X(k) = T2t[line][k] for k <= R; output Re y -> cgrid[line][m].
+//   MODE 1 (rows): two rows per workgroup, lines 2b and 2b+1, with half spectra
+//     H(k) = T2t[line][k], k <= R, whose real transforms are wanted: Re of the
+//     transform of H is the transform of the Hermitian X(k) = (H(k) + conj H(-k))/2,
+//     so one complex transform of X1 + i X2 gives row 2b in its real part and row
+//     2b+1 in its imaginary part (half the transforms).
 // ---------------------------------------------------------------------------
 template <class R, int MODE>
 __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t2(const typename cplx<R>::T *__restrict__ in, void *__restrict__ outv, const int32_t *__restrict__ col_off,
@@ -443,7 +447,8 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t2(const ty
     C *lds = reinterpret_cast<C *>(smem);
     double2 *tt = reinterpret_cast<double2 *>(smem + (size_t)lpad(g.Q) * sizeof(C));   // two-level twiddle table
     tw_stage(tt, tw, g.nf);
-    const int line = blockIdx.x, tid = threadIdx.x, T = g.Q >> 4, L = ilog2(g.Q);
+    const int line = MODE == 1 ? 2 * blockIdx.x : blockIdx.x, tid = threadIdx.x, T = g.Q >> 4, L = ilog2(g.Q);
+    const bool two = MODE == 1 && line + 1 < g.Lpad;   // second row of the pair exists
     int off = 0, cnt = 0, ny0 = 0;
     C cx{1, 0};
     if (MODE == 0) {
@@ -470,7 +475,15 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t2(const ty
                 }
             } else {
                 const int k = g.P * kp + s;
-                if (k <= g.R) val = in[(size_t)line * (g.R + 1) + k];
+                const C *h1r = in + (size_t)line * (g.R + 1), *h2r = h1r + (g.R + 1);
+                if (k <= g.R) {                                   // (H1 + i H2)/2; k = 0: Re H1 + i Re H2
+                    const C h1 = h1r[k], h2 = two ? h2r[k] : C{0, 0};
+                    val = k == 0 ? C{h1.x, h2.x} : C{R(0.5) * (h1.x - h2.y), R(0.5) * (h1.y + h2.x)};
+                } else if (k >= g.nf - g.R) {                     // (conj H1 + i conj H2)/2 at -k
+                    const int kk = g.nf - k;
+                    const C h1 = h1r[kk], h2 = two ? h2r[kk] : C{0, 0};
+                    val = C{R(0.5) * (h1.x + h2.y), R(0.5) * (h2.x - h1.y)};
+                }
             }
             v[r] = val;
         }
@@ -490,8 +503,12 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t2(const ty
     for (int i = 0; i < 16; ++i) {
         const int m = tid + i * T;
         if (m >= g.Lpad) continue;
-        if (MODE == 0) reinterpret_cast<C *>(outv)[(size_t)line * g.Lpad + m] = acc[i];
-        else reinterpret_cast<R *>(outv)[(size_t)line * g.Lpad + m] = acc[i].x;
+        if (MODE == 0) {
+            reinterpret_cast<C *>(outv)[(size_t)line * g.Lpad + m] = acc[i];
+        } else {
+            reinterpret_cast<R *>(outv)[(size_t)line * g.Lpad + m] = acc[i].x;
+            if (two) reinterpret_cast<R *>(outv)[(size_t)(line + 1) * g.Lpad + m] = acc[i].y;
+        }
     }
 }
 
@@ -1793,11 +1810,11 @@ hipError_t launch_fft_rows2(Plan &p)
     const unsigned T = (unsigned)(g.Q / 16);
     if (p.precision == WFP2D_PREC_MIXED) {
         transpose<float2>(p, p.d_T2, p.d_T2t, g.R + 1, g.Lpad);
-        hipLaunchKernelGGL((k_fft_t2<float, 1>), dim3(g.Lpad), dim3(T), sh, p.stream, (const float2 *)p.d_T2t, p.d_cgrid, nullptr,
+        hipLaunchKernelGGL((k_fft_t2<float, 1>), dim3((g.Lpad + 1) / 2), dim3(T), sh, p.stream, (const float2 *)p.d_T2t, p.d_cgrid, nullptr,
                            nullptr, (const float2 *)p.d_corr, (const double2 *)p.d_tw, g);
     } else {
         transpose<double2>(p, p.d_T2, p.d_T2t, g.R + 1, g.Lpad);
-        hipLaunchKernelGGL((k_fft_t2<double, 1>), dim3(g.Lpad), dim3(T), sh, p.stream, (const double2 *)p.d_T2t, p.d_cgrid, nullptr,
+        hipLaunchKernelGGL((k_fft_t2<double, 1>), dim3((g.Lpad + 1) / 2), dim3(T), sh, p.stream, (const double2 *)p.d_T2t, p.d_cgrid, nullptr,
                            nullptr, (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
     }
     return hipGetLastError();
