@@ -74,9 +74,14 @@ typedef struct {
     int32_t spread_tile; /* type-1 spreading tile shape, 0 = default (3); see wfp2d_set_spread_tile */
     /* Local part (Sec. 6, eq. local2): 0 (default) = store the list of source-target
      * pairs with r < delta, with each pair's time-step panel and Chebyshev coordinate,
-     * once at init (12 bytes per pair) when it takes at most half of the free device
-     * memory, and stream it at every step; -1 = never (pairs are found at every step
-     * from the cell lists).  Both give the same sums up to the order of additions. */
+     * once at init (8 bytes per pair; 4 bytes plus one weight per lookup level for the
+     * pairs with r < dt/2) when it takes at most half of the free device memory and
+     * the local tables fit the list kernel (W <= 64), and stream it at every step;
+     * -1 = never (pairs are found at every step from the cell lists).  Both give the
+     * same sums up to the order of additions, except that a mixed-precision plan with
+     * stored pairs evaluates only the leading Chebyshev terms of each panel whose
+     * dropped tail is at most 1e-3 tol of the largest coefficient (info.cheb_degree).
+     * info.local_path reports the path taken. */
     int32_t local_pairs;
 } wfp2d_opts;
 
