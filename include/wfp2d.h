@@ -302,6 +302,13 @@ wfp2d_status wfp2d_get_timing(wfp2d_plan plan, double *ms, int64_t *launches, in
  *     out = [k][2] = (phi, phi').
  *   7 layout of the local-weight tables: in as 4; out = {sub-panels, regular
  *     sub-panels, levels, max relative fit error, log2 splits of panel 0..W-1}.
+ *   8 the weights as a mixed-precision plan with stored pair lists evaluates
+ *     them: in as 4; out = {terms, tail bound, largest coefficient, then
+ *     [k][n_levels]}, where the regular sub-panels keep only their leading
+ *     `terms` Chebyshev coefficients (the smallest of 12, 14, 16 whose dropped
+ *     coefficients sum, per sub-panel over the largest magnitude per term, to at
+ *     most 1e-3 tol of the largest coefficient; else all) and the tail bound is
+ *     that sum for the returned count.
  * Returns ERR_ARG for an unknown what, short buffers or bad parameters; on
  * success out_count (if not NULL) receives the number of doubles written. */
 wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, double *out, int64_t n_out,

@@ -623,25 +623,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         // scale of the fit criterion of the tables).  Measured, the field then moves by about
         // ten times that bound, two orders of magnitude below tol; FP64 plans use every
         // stored term.
-        const int nl = LT.nlev, D = kChebDeg;
-        double gmax = 0.0;
-        for (double v : LT.coef) gmax = std::max(gmax, std::fabs(v));
-        for (int nt : {12, 14, 16}) {
-            double tail = 0.0;
-            for (int k = 0; k < p.n_reg; ++k) {
-                double t = 0.0;
-                for (int c = nt; c < D; ++c) {
-                    double cm = 0.0;
-                    for (int d = 0; d < nl; ++d) cm = std::max(cm, std::fabs(LT.coef[((size_t)k * nl + d) * D + c]));
-                    t += cm;
-                }
-                tail = std::max(tail, t);
-            }
-            if (tail <= 1e-3 * p.tol * gmax) {
-                p.local_terms = nt;
-                break;
-            }
-        }
+        p.local_terms = local_table_terms(LT, p.tol);
     }
     // local-pair count (reported; without pair lists the local kernel finds pairs through the cell lists)
     if (!p.local_pairs) {
@@ -1368,6 +1350,26 @@ wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, doubl
                 LocalTable T = build_local_table(LW, 40, 1e-11);
                 for (int64_t i = 0; i < k; ++i) local_table_eval(T, dt, W, in[5 + i], out + i * LW.nlev);
             }
+            break;
+        }
+        case 8: {
+            if (n_in < 5) fail(WFP2D_ERR_ARG, "need dt, W, p, lookahead, tol");
+            const double dt = in[0], tol = in[4];
+            const int W = (int)in[1], p = (int)in[2];
+            int look = (int)in[3];
+            if (look < 0) look = (p + 1) / 2 - 1;
+            if (!(dt > 0) || W < 2 || p < 2 || !(tol > 0 && tol < 1)) fail(WFP2D_ERR_ARG, "bad local parameters");
+            Blend phi(W * dt, std::log(1.0 / tol), 160);
+            LocalWeights LW(dt, W, p, -look, phi);
+            LocalTable T = build_local_table(LW, 40, 1e-11);
+            double tail = 0.0, cmax = 0.0;
+            const int terms = local_table_terms(T, tol, &tail, &cmax);
+            const int64_t k = n_in - 5;
+            need(3 + k * T.nlev);
+            out[0] = terms;
+            out[1] = tail;
+            out[2] = cmax;
+            for (int64_t i = 0; i < k; ++i) local_table_eval(T, dt, W, in[5 + i], out + 3 + i * T.nlev, terms);
             break;
         }
         case 7: {

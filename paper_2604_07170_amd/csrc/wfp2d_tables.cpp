@@ -400,7 +400,7 @@ LocalTable build_local_table(const LocalWeights &LW, int n_dy, double rel_tol)
     return T;
 }
 
-void local_table_eval(const LocalTable &T, double dt, int W, double r, double *out)
+void local_table_eval(const LocalTable &T, double dt, int W, double r, double *out, int nterm_regular)
 {
     const double rr = r / dt;
     int sub;
@@ -417,7 +417,37 @@ void local_table_eval(const LocalTable &T, double dt, int W, double r, double *o
     const SubPanel &sp = T.subs[sub];
     const double v = sp.c > 0.0 ? std::sqrt(std::max(0.0, sp.c - r)) : r;
     const double xc = std::min(1.0, std::max(-1.0, (2.0 * v - sp.ua - sp.ub) * sp.inv));
-    for (int d = 0; d < T.nlev; ++d) out[d] = cheb_eval(&T.coef[((size_t)sub * T.nlev + d) * kChebDeg], kChebDeg, xc);
+    const int nt = sub < T.dy_base ? std::min(std::max(nterm_regular, 1), kChebDeg) : kChebDeg;
+    for (int d = 0; d < T.nlev; ++d) out[d] = cheb_eval(&T.coef[((size_t)sub * T.nlev + d) * kChebDeg], nt, xc);
+}
+
+int local_table_terms(const LocalTable &T, double tol, double *tail_out, double *cmax_out)
+{
+    const int nl = T.nlev, D = kChebDeg;
+    double cmax = 0.0;
+    for (double v : T.coef) cmax = std::max(cmax, std::fabs(v));
+    auto tail_of = [&](int nt) {
+        double tail = 0.0;
+        for (int k = 0; k < T.dy_base; ++k) {
+            double t = 0.0;
+            for (int c = nt; c < D; ++c) {
+                double cm = 0.0;
+                for (int d = 0; d < nl; ++d) cm = std::max(cm, std::fabs(T.coef[((size_t)k * nl + d) * D + c]));
+                t += cm;
+            }
+            tail = std::max(tail, t);
+        }
+        return tail;
+    };
+    int terms = D;
+    for (int nt : {12, 14, 16})
+        if (tail_of(nt) <= 1e-3 * tol * cmax) {
+            terms = nt;
+            break;
+        }
+    if (tail_out) *tail_out = tail_of(terms);
+    if (cmax_out) *cmax_out = cmax;
+    return terms;
 }
 
 // ---------------------------------------------------------------------------

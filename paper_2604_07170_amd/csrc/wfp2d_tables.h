@@ -56,8 +56,17 @@ struct LocalTable {
 };
 
 LocalTable build_local_table(const LocalWeights &LW, int n_dy, double rel_tol);
-// eta_d(r) from the table with the same sub-panel lookup as the local kernel
-void local_table_eval(const LocalTable &T, double dt, int W, double r, double *out);
+// eta_d(r) from the table with the same sub-panel lookup as the local kernel; the regular
+// sub-panels (index < dy_base) use their leading nterm_regular coefficients
+void local_table_eval(const LocalTable &T, double dt, int W, double r, double *out, int nterm_regular = kChebDeg);
+
+// Leading Chebyshev terms kept on the regular sub-panels by a mixed-precision plan: the
+// smallest of 12, 14, 16 for which the dropped terms' bound (per sub-panel, the sum over the
+// dropped terms of their largest magnitude over levels; the worst sub-panel) is at most
+// 1e-3 tol times the largest coefficient of the table, else kChebDeg.  Since |T_c| <= 1 on
+// [-1, 1], that bound also bounds the change of every eta_d.  tail_out and cmax_out (if not
+// NULL) receive the bound for the returned count and the largest coefficient.
+int local_table_terms(const LocalTable &T, double tol, double *tail_out = nullptr, double *cmax_out = nullptr);
 
 double es_kernel(double z, int w, double beta);
 void es_fourier(int w, double beta, int64_t nf, int64_t R, std::vector<double> &out);

@@ -4,9 +4,9 @@
 * the sum-of-exponentials rule of Sec. 2.3 against the closed form 1/sqrt(t^2-r^2);
 * the Hankel coefficients of eq. H against Table 1, and their kappa = 0 limit
   against a radial integral done independently with scipy;
-* the local-part weights: the Chebyshev tables against direct quadrature, and
-  the direct quadrature against closed forms (polynomial sigma is integrated
-  exactly; phi = 0 gives acosh);
+* the local-part weights: the Chebyshev tables against direct quadrature, also
+  as a mixed-precision plan truncates them, and the direct quadrature against
+  closed forms (polynomial sigma is integrated exactly; phi = 0 gives acosh);
 * the blending function against its defining integral.
 """
 import math
@@ -98,6 +98,35 @@ def _eta(what, r, dt, W, p, look, tol):
     r = np.atleast_1d(r)
     v = pa.host_eval(what, [dt, W, p, look, tol, *r], 100 * r.size)
     return v.reshape(r.size, -1)
+
+
+@pytest.mark.parametrize("dt,W,p", [(0.05, 24, 20), (8 / 7150, 16, 20)])
+def test_mixed_precision_term_truncation(dt, W, p):
+    """A mixed-precision plan with stored pairs evaluates the regular sub-panels
+    (r >= dt/2) from their leading Chebyshev terms only.  At these two
+    configurations it keeps 16 of 20.  Since |T_c| <= 1, the weights then move by
+    at most the reported tail bound, which the rule keeps within 1e-3 tol of the
+    largest coefficient.  The sub-panels below dt/2 are untouched, and the weights
+    stay within 1e-2 tol of the largest weight against direct quadrature (Sec. 6)."""
+    tol = 1e-7
+    rng = np.random.default_rng(7)
+    r = np.concatenate([rng.uniform(0.5, W, 300) * dt, dt * (np.arange(1, W) + 0.5),
+                        dt * np.geomspace(1e-6, 0.49, 10)])
+    v = pa.host_eval(8, [dt, W, p, -1, tol, *r], 3 + 100 * r.size)
+    terms, tail, cmax = v[0], v[1], v[2]
+    trunc = v[3:].reshape(r.size, -1)
+    full = _eta(5, r, dt, W, p, -1, tol)
+    direct = _eta(4, r, dt, W, p, -1, tol)
+    dyadic = r < 0.5 * dt
+    top = np.abs(direct[~dyadic]).max()
+    diff = np.abs(trunc - full).max()
+    print(f"dt={dt:.4g} W={W}: {terms:.0f} terms, tail bound {tail:.2e} (largest coefficient {cmax:.2f}), "
+          f"weights moved by {diff:.2e}, vs direct quadrature {np.abs(trunc - direct).max() / top:.2e} of the largest weight")
+    assert terms == 16
+    assert tail <= 1e-3 * tol * cmax
+    assert 0.0 < diff <= tail * (1 + 1e-9) + 1e-14 * top
+    assert np.array_equal(trunc[dyadic], full[dyadic])
+    assert np.abs(trunc - direct).max() <= 1e-2 * tol * top
 
 
 def test_local_weights_integrate_polynomials_exactly():
