@@ -1,0 +1,117 @@
+"""The near- and far-history recurrences in the form the kernels run them, against
+the sums they stand for (CPU, numpy, with the library's own parameters, blend and
+sum-of-exponentials nodes).
+
+Near history (Sec. 4.3; eq. alphak discretised by the trapezoid rule on the time
+grid):
+    alpha_n(kappa) = dt sum_{l=0}^{LA+W} w_l sin(kappa l dt)/kappa S_{n-l},
+with w_l = phi(l dt) on the opening edge l < W, 1 inside, and phi((LA+W-l) dt) on
+the closing edge LA < l <= LA+W.  The kernel holds the interior part l = W..LA as
+the pair D = sum sin(kappa l dt)/kappa S_{n-l}, C = sum cos(kappa l dt) S_{n-l},
+advanced by the exact rotation of the Lemma of Sec. 4.3 (one sample enters at
+l = W-1, one leaves at l = LA), and adds both edges as (W-1)-tap FIRs
+(the structure of eq. hggrid).
+
+Far history (Sec. 5; eqs. beta, betaEvolution, alphaFApprox, with the same
+trapezoid rule):
+    alpha_F,n = sum_q H_q dt sum_{m > LA} v_m e^{-lambda_q (m dt - A)} S_{n-m},
+v_m = 1 - phi((LA+W-m) dt) on the edge LA < m < LA+W and 1 beyond.  The kernel
+holds the part m >= LA+W in one decaying state per node (eq. betaEvolution) and
+folds the edge with H into a (W-1)-tap FIR per wavenumber.
+
+Both recurrences must reproduce the sums to rounding, for wavenumbers from 0 (the
+sin(x)/x -> x limit) to the Nyquist limit K = pi/dt.
+"""
+import numpy as np
+import pytest
+
+pa = pytest.importorskip("paper_2604_07170_amd")
+
+
+def _setup(dt, W, tol, p):
+    v = pa.host_eval(1, [dt, W, tol, p, -1, 1.0, 0.0, 80.0], 12)
+    delta, b, A, LA = v[0], v[1], v[2], int(round(v[8]))
+    phi = lambda t: np.array([pa.host_eval(6, [delta, b, x], 2)[0] for x in np.atleast_1d(t)])
+    return delta, b, A, LA, phi
+
+
+def _sinc_dt(kap, l, dt):
+    """sin(kappa l dt)/kappa, with its kappa -> 0 limit l dt."""
+    safe = np.where(kap > 0, kap, 1.0)
+    return np.where(kap > 0, np.sin(kap * l * dt) / safe, l * dt)
+
+
+@pytest.mark.parametrize("dt,W,tol,p", [(0.05, 24, 1e-7, 20), (0.05, 12, 1e-4, 6)])
+def test_near_recurrence_equals_trapezoid_sum(dt, W, tol, p):
+    delta, b, A, LA, phi = _setup(dt, W, tol, p)
+    rng = np.random.default_rng(3)
+    kap = np.array([0.0, 0.683, 5.3, 40.1, np.pi / dt])
+    nt = LA + 3 * W + 40
+    S = rng.standard_normal((nt + 1, kap.size)) + 1j * rng.standard_normal((nt + 1, kap.size))
+    S[0] = 0.0
+    at = lambda m: S[m] if m >= 1 else np.zeros(kap.size, complex)
+
+    w = np.ones(LA + W + 1)
+    w[:W] = phi(np.arange(W) * dt)
+    w[LA + 1:] = phi((LA + W - np.arange(LA + 1, LA + W + 1)) * dt)
+    ker = np.array([dt * w[l] * _sinc_dt(kap, l, dt) for l in range(LA + W + 1)])
+    direct = np.array([sum(ker[l] * at(n - l) for l in range(LA + W + 1)) for n in range(nt + 1)])
+
+    c, s = np.cos(kap * dt), np.sin(kap * dt)
+    s_k = _sinc_dt(kap, 1, dt)
+    fir_open = [dt * w[l] * _sinc_dt(kap, l, dt) for l in range(1, W)]
+    fir_close = [dt * w[l] * _sinc_dt(kap, l, dt) for l in range(LA + 1, LA + W)]
+    D = np.zeros(kap.size, complex)
+    C = np.zeros(kap.size, complex)
+    err = 0.0
+    for n in range(nt + 1):
+        a = dt * D + sum(fir_open[l - 1] * at(n - l) for l in range(1, W)) \
+            + sum(fir_close[l - LA - 1] * at(n - l) for l in range(LA + 1, LA + W))
+        err = max(err, np.abs(a - direct[n]).max())
+        # the sample at delay W-1 enters the interior, the one at delay LA leaves it;
+        # then one step of the exact rotation moves every delay up by one
+        Dn = D + _sinc_dt(kap, W - 1, dt) * at(n - W + 1) - _sinc_dt(kap, LA, dt) * at(n - LA)
+        Cn = C + np.cos(kap * (W - 1) * dt) * at(n - W + 1) - np.cos(kap * LA * dt) * at(n - LA)
+        D = c * Dn + s_k * Cn
+        C = c * Cn - kap * s * Dn
+    scale = np.abs(direct).max()
+    print(f"near recurrence: LA = {LA}, max error {err / scale:.2e} of the largest value")
+    assert err <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("dt,W,tol,p", [(0.05, 24, 1e-7, 20)])
+def test_far_recurrence_equals_windowed_sum(dt, W, tol, p):
+    delta, b, A, LA, phi = _setup(dt, W, tol, p)
+    lam = pa.host_eval(2, [], 1280)[:640]
+    rng = np.random.default_rng(4)
+    nk = 4
+    H = rng.standard_normal((nk, lam.size)) * np.exp(-1e-3 * lam)[None, :]
+    nt = LA + 3 * W + 40
+    S = rng.standard_normal((nt + 1, nk)) + 1j * rng.standard_normal((nt + 1, nk))
+    S[0] = 0.0
+    at = lambda m: S[m] if m >= 1 else np.zeros(nk, complex)
+
+    def v(m):
+        return 1.0 - phi((LA + W - m) * dt)[0] if m < LA + W else 1.0
+
+    direct = []
+    for n in range(nt + 1):
+        tot = np.zeros(nk, complex)
+        for m in range(LA + 1, n + 1):
+            tot += (H @ (dt * v(m) * np.exp(-lam * (m * dt - A)))) * at(n - m)
+        direct.append(tot)
+    direct = np.array(direct)
+
+    chi = [H @ (dt * v(m) * np.exp(-lam * (m * dt - A))) for m in range(LA + 1, LA + W)]
+    decay = np.exp(-lam * dt)
+    inject = dt * np.exp(-lam * ((LA + W - 1) * dt - A))
+    B = np.zeros((nk, lam.size), complex)
+    err = 0.0
+    for n in range(nt + 1):
+        aF = np.sum(H * B, axis=1) + sum(chi[m - LA - 1] * at(n - m) for m in range(LA + 1, LA + W))
+        err = max(err, np.abs(aF - direct[n]).max())
+        # the sample at delay LA+W-1 enters the state, which then decays by one step
+        B = decay[None, :] * (B + inject[None, :] * at(n - LA - W + 1)[:, None])
+    scale = np.abs(direct).max()
+    print(f"far recurrence: LA = {LA}, max error {err / scale:.2e} of the largest value")
+    assert scale > 0 and err <= 1e-12 * scale
