@@ -223,8 +223,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding of the "
-                                   "method is described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the sharding of the method over "
+                                   "several GPUs is not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

@@ -1,7 +1,7 @@
 """Parity of the HIP path with the oracle (GPU).
 
 End-to-end: relative L2 error over all sampled (target, step) pairs <= 1e-6,
-the accuracy the method targets at eps = 1e-7 (Sec. 5: "around 6 digits").
+the accuracy the method targets at eps = 1e-7 (about six correct digits, Sec. 5).
 Stages: the type-1 NUFFT against the direct Fourier sum of eq. sighat, the
 near-history coefficients against eq. alphak evaluated by quadrature.
 """
