@@ -1,0 +1,51 @@
+"""Host logic of the benchmark (CPU): the committed HBM byte counters are used for
+`roofline.traffic` only while the kernels' code is the code they were taken on."""
+import os
+import re
+import shutil
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.fixture
+def tree(tmp_path, monkeypatch):
+    """A copy of the kernels source and of the counters summary under a scratch root."""
+    (tmp_path / "paper_2604_07170_amd" / "csrc").mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    src = os.path.join("paper_2604_07170_amd", "csrc", "wfp2d_kernels.hip")
+    prof = os.path.join("profiles", "hbm_counters_cfg4_M1e6_mixed.md")
+    shutil.copy(os.path.join(ROOT, src), tmp_path / src)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # the copied summary is marked as taken on the copied source, whatever the committed state
+    text = re.sub(r"code sha256 prefix: [0-9a-f]{16}", "code sha256 prefix: " + bench.kernels_digest(),
+                  open(os.path.join(ROOT, prof)).read())
+    (tmp_path / prof).write_text(text)
+    return tmp_path / src
+
+
+def test_lookup_by_kernel_name(tree):
+    assert bench.measured_traffic("k_near") is not None
+    assert bench.measured_traffic("k_no_such_kernel") is None
+
+
+def test_comment_edits_keep_and_code_edits_drop_the_counters(tree):
+    base = bench.kernels_digest()
+    bytes0 = bench.measured_traffic("k_local_pairs")
+    assert bytes0 is not None and bytes0 > 1e9
+    text = tree.read_text()
+    tree.write_text("// a new comment line\n\n" + text.replace("{\n", "{  /* note */\n", 1))
+    assert bench.kernels_digest() == base
+    assert bench.measured_traffic("k_local_pairs") == bytes0
+    tree.write_text(text + "\nstatic int wfp2d_changed_code = 1;\n")
+    assert bench.kernels_digest() != base
+    assert bench.measured_traffic("k_local_pairs") is None
+
+
+def test_missing_summary_gives_no_traffic(tree):
+    os.remove(tree.parents[2] / "profiles" / "hbm_counters_cfg4_M1e6_mixed.md")
+    assert bench.measured_traffic("k_local_pairs") is None
