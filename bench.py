@@ -458,7 +458,7 @@ def main():
         log(f"[bench] oracle sample {t_cpu:.1f}s on {nth} threads; GPU vs oracle rel err {sample_err:.2e}")
 
     out = {
-        "metric": "source*timesteps/sec at 1e-6 rel L2 error; % of HBM roofline",
+        "metric": "source\u00b7timesteps/sec at 1e-6 rel L2 error; % of HBM roofline (mixed vs FP64)",
         "value": value,
         "unit": "source*steps/s",
         "n_gpus": 1,
