@@ -12,7 +12,9 @@ Contents
   compensated summation.  Optional windows give the local / near / far /
   history components of eq. split.
 * :func:`phi` — the blending function of eq. KBblending.
-* :mod:`oracle.dft` — direct (non-fast) Fourier sums for the stage checks.
+
+The stage check of the type-1 transform compares with the direct Fourier sum
+of eq. sighat, written out in that test (a matrix-vector product in numpy).
 """
 from __future__ import annotations
 
