@@ -21,7 +21,9 @@ def test_errors_are_status_codes_without_a_device():
     plan = ctypes.c_void_p()
     xy = (ctypes.c_double * 2)(0.0, 0.0)
     # bad arguments are rejected before any device call
-    assert lib.wfp2d_init(ctypes.byref(plan), 0, xy, 1, xy, 0.1, 16, 1e-7, None) == -1
+    assert lib.wfp2d_init(ctypes.byref(plan), 0, xy, 1, xy, 0.1, 16, 1e-7, None) == -1   # no sources
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 0, xy, 0.1, 16, 1e-7, None) == -1   # no targets
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, None, 1, xy, 0.1, 16, 1e-7, None) == -1  # no coordinates
     assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, -0.1, 16, 1e-7, None) == -1
     assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.1, 16, 0.5, None) == -1
     far = (ctypes.c_double * 2)(1.5, 0.0)
