@@ -309,6 +309,10 @@ wfp2d_status wfp2d_get_timing(wfp2d_plan plan, double *ms, int64_t *launches, in
  *     coefficients sum, per sub-panel over the largest magnitude per term, to at
  *     most 1e-3 tol of the largest coefficient; else all) and the tail bound is
  *     that sum for the returned count.
+ *   9 Fourier transform of the spreading kernel (the NUFFT deconvolution
+ *     factors, R18): in = {w, beta, nf, n_1..n_k}, |n_i| < nf/2; out[i] =
+ *     int psi(z) cos(2 pi n_i z / nf) dz over |z| <= w/2, psi the
+ *     exponential-of-semicircle kernel of width w and shape beta.
  * Returns ERR_ARG for an unknown what, short buffers or bad parameters; on
  * success out_count (if not NULL) receives the number of doubles written. */
 wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, double *out, int64_t n_out,

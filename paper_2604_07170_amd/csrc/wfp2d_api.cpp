@@ -1389,6 +1389,21 @@ wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, doubl
             for (int k = 0; k < W; ++k) out[4 + k] = (double)T.panel_l2n[k];
             break;
         }
+        case 9: {
+            if (n_in < 3) fail(WFP2D_ERR_ARG, "need w, beta, nf");
+            const int w = (int)in[0];
+            const double beta = in[1];
+            const int64_t nf = (int64_t)in[2];
+            if (w < 2 || w > 16 || !(beta > 0) || nf < 2 * w) fail(WFP2D_ERR_ARG, "bad spreading kernel parameters");
+            int64_t R = 0;
+            for (int64_t i = 3; i < n_in; ++i) R = std::max<int64_t>(R, std::llabs((int64_t)in[i]));
+            if (R >= nf / 2) fail(WFP2D_ERR_ARG, "frequency index beyond nf/2");
+            std::vector<double> ft;
+            es_fourier(w, beta, nf, R, ft);
+            need(n_in - 3);
+            for (int64_t i = 3; i < n_in; ++i) out[i - 3] = ft[(int64_t)in[i] + R];
+            break;
+        }
         case 6: {
             if (n_in < 2) fail(WFP2D_ERR_ARG, "need width, b");
             Blend B(in[0], in[1], 160);

@@ -7,7 +7,9 @@
 * the local-part weights: the Chebyshev tables against direct quadrature, also
   as a mixed-precision plan truncates them, and the direct quadrature against
   closed forms (polynomial sigma is integrated exactly; phi = 0 gives acosh);
-* the blending function against its defining integral.
+* the blending function against its defining integral;
+* the NUFFT deconvolution factors (the spreading kernel's Fourier transform)
+  against adaptive quadrature.
 """
 import math
 import os
@@ -127,6 +129,22 @@ def test_mixed_precision_term_truncation(dt, W, p):
     assert 0.0 < diff <= tail * (1 + 1e-9) + 1e-14 * top
     assert np.array_equal(trunc[dyadic], full[dyadic])
     assert np.abs(trunc - direct).max() <= 1e-2 * tol * top
+
+
+@pytest.mark.parametrize("w,nf", [(8, 480), (12, 12288), (16, 4608)])
+def test_spreading_kernel_transform(w, nf):
+    """The NUFFT deconvolution factors (reading R18): the Fourier transform of the
+    exponential-of-semicircle kernel psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)),
+    |z| <= w/2, beta = 2.30 w, at grid frequencies n up to nf/4 (the band the
+    oversampled grid keeps), against adaptive quadrature of that definition."""
+    beta = 2.30 * w
+    ns = [0, 1, 7, nf // 16, nf // 8, nf // 4]
+    got = pa.host_eval(9, [w, beta, nf, *ns], len(ns))
+    for n, g in zip(ns, got):
+        f = lambda z: math.exp(beta * (math.sqrt(max(0.0, 1 - (2 * z / w) ** 2)) - 1)) * \
+            math.cos(2 * math.pi * n * z / nf)
+        ref, _ = integrate.quad(f, -w / 2, w / 2, limit=1000, epsabs=1e-300, epsrel=1e-13)
+        assert g == pytest.approx(ref, rel=1e-12), (w, nf, n)      # measured <= 1.2e-14
 
 
 def test_local_weights_integrate_polynomials_exactly():
