@@ -56,6 +56,9 @@ def _load():
         lib.oracle_phi.argtypes = [ctypes.c_int64, d, ctypes.c_double, ctypes.c_double, d, d]
         lib.oracle_phi.restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_sig_support.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, d, d]
+        lib.oracle_sig_support.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -108,6 +111,15 @@ def u_workload(w, target_idx, times, **kw):
     ts = np.tile(times, len(target_idx))
     out = u_direct(w.src, w.family, w.amp, w.t0, w.omega, w.s, xs, ts, **kw)
     return out.reshape(len(target_idx), len(times))
+
+
+def sig_support(family, amp, t0, omega, s=0.0):
+    """(start, end): the oracle takes a signature as exactly zero for t <= start and t >= end."""
+    lib = _load()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib.oracle_sig_support(int(family), float(amp), float(t0), float(omega), float(s),
+                           ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def phi(t, delta, b):

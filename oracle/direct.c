@@ -442,6 +442,16 @@ int oracle_phi(int64_t n, const double *t, double delta, double b, double *phi, 
     return 0;
 }
 
+/* The numerical support [start, end] of a signature as the quadrature uses it
+ * (sigma is taken as exactly zero outside it), for tests of the cut-offs. */
+int oracle_sig_support(int32_t fam, double A, double t0, double w, double s, double *start, double *end)
+{
+    sig_t g = {fam, A, t0, w, s};
+    if (start) *start = sig_start(&g);
+    if (end) *end = sig_end(&g);
+    return 0;
+}
+
 int oracle_threads(void)
 {
 #ifdef _OPENMP

@@ -195,3 +195,98 @@ def test_spatial_fourier_transform_closed_form(k):
     print(f"k = {k}: transform of the oracle field {uhat:.12e}, closed form {closed:.12e}, "
           f"rel diff {abs(uhat - closed) / abs(closed):.1e}")
     assert abs(closed) > 1e-4 and abs(uhat - closed) <= 1e-11 * abs(closed)   # measured 2e-14
+
+
+# ---------------------------------------------------------------------------
+# The signature-support cut-offs.  The oracle takes family E as exactly zero for
+# t <= t0 - 2 (when t0 > 2) and family G as exactly zero for t >= t0 + 22.5 s.
+# These tests place the cut inside the integration range, so a cut moved inward
+# (dropping a non-negligible part of sigma) changes u beyond the QUADPACK bound.
+# ---------------------------------------------------------------------------
+
+def _erfc_half(x):
+    return 0.5 * math.erfc(x)
+
+
+@pytest.mark.parametrize("t0", [3.0, 5.0, 2.0001])
+def test_family_e_support_start_is_below_1e40(t0):
+    # eq. exampleDensities: sigma = A (1 + erf(5 (t - t0)))/2 sin(...), so below the cut
+    # |sigma| <= |A| erfc(5 (t0 - t))/2 <= erfc(10)/2 ~ 1e-45
+    start, end = oracle.sig_support(FAMILY_E, 1.0, t0, 50.0)
+    assert start == pytest.approx(t0 - 2.0, abs=1e-15) and math.isinf(end)
+    assert _erfc_half(5.0 * (t0 - start)) < 1e-40
+    # the cut is as far in as a 1e-40 bound allows, up to a margin: not at t0 - 1.5 or closer
+    assert start <= t0 - 1.9
+
+
+def test_family_e_support_start_is_zero_for_early_onsets():
+    start, _ = oracle.sig_support(FAMILY_E, 1.0, 1.3, 50.0)
+    assert start == 0.0            # sigma(t <= 0) = 0 (eq. wave2d: zero initial data)
+
+
+@pytest.mark.parametrize("s", [0.25, 0.05])
+def test_family_g_support_end_is_below_1e40(s):
+    t0 = 0.4
+    start, end = oracle.sig_support(FAMILY_G, 1.0, t0, 4 * math.pi, s)
+    assert start == t0
+    assert end == pytest.approx(t0 + 22.5 * s, rel=1e-15)
+    c = t0 + 8.5 * s
+    assert math.exp(-((end - c) ** 2) / (2 * s * s)) < 1e-40
+    assert end >= t0 + 22.0 * s
+
+
+@pytest.mark.parametrize("t0,w,r,t", [
+    (3.0, 31.4, 0.21, 4.6),       # the cut at t0 - 2 = 1 lies inside [r, t]: tau up to 3.6
+    (5.0, 47.1, 0.05, 6.3),       # tau up to 3.3 reaches below the cut at 3
+    (2.6, 94.2, 0.4, 3.9),
+])
+def test_family_e_late_onset_against_quadpack(t0, w, r, t):
+    """Independent integration of the untruncated eq. exampleDensities signature.
+    With t0 > 2 the oracle starts each integral at t - tau = t0 - 2; QUADPACK sees the
+    whole of [r, t].  A cut moved inward by 0.5 or more leaves out erfc(7.5)/2-sized or
+    larger pieces of the erf ramp; one at t0 - 1 already shifts u by ~1e-12 relative,
+    and anything above the 2e-11 tolerance fails here."""
+    from wfp_workloads import sigma_np
+    sig = one(FAMILY_E, A=1.0, t0=t0, w=w)
+    f = lambda tau: sigma_np(np.array([FAMILY_E]), np.array([1.0]), np.array([t0]), np.array([w]),
+                             np.array([0.0]), t - tau)[0] / math.sqrt(tau + r)
+    # split at the erf ramp so that QUADPACK resolves it
+    pts = sorted({r, max(r, t - t0 - 0.6), max(r, t - t0 + 0.6), t})
+    val = 0.0
+    for a, b in zip(pts[:-1], pts[1:]):
+        if b > a:
+            v, _ = integrate.quad(lambda x: f(x) * (1.0 / math.sqrt(x - r) if a > r else 1.0), a, b,
+                                  **({} if a > r else dict(weight="alg", wvar=(-0.5, 0.0))),
+                                  limit=5000, epsabs=1e-15, epsrel=1e-13)
+            val += v
+    u = u1((0.0, 0.0), (r, 0.0), t, sig)
+    assert abs(val) > 1e-3
+    assert u == pytest.approx(val / (2 * math.pi), rel=2e-11, abs=1e-15)
+    # and the ramp below the cut is what a wrongly placed cut would drop: its size
+    lost = abs(integrate.quad(lambda x: f(x) / math.sqrt(x - r), t - t0 + 0.2, t - t0 + 2.0,
+                              limit=2000)[0])
+    assert lost > 1e-6 * abs(val)
+
+
+@pytest.mark.parametrize("s,w,t0,r,extra", [(0.25, 4 * math.pi, 0.3, 0.4, 1.0),
+                                             (0.05, 20 * math.pi, 0.1, 0.013, 0.37)])
+def test_family_g_after_envelope_against_mpmath(s, w, t0, r, extra):
+    """t - r beyond t0 + 22.5 s: the whole envelope lies inside [r, t], and the oracle starts
+    each integral at t - tau = t0 + 22.5 s.  The reference is 30-digit tanh-sinh quadrature
+    (mpmath) of the signature over its whole envelope, in the variable x = t - tau where the
+    kernel 1/sqrt(tau^2 - r^2) is smooth; QUADPACK in double precision loses ~1e-12 of this
+    cancelling integral to roundoff.  A support end moved inward to t0 + 14 s would drop a
+    tail of relative size 1e-9 or more (checked below), far above the 1e-12 tolerance."""
+    import mpmath as mp
+    sig = one(FAMILY_G, A=1.0, t0=t0, w=w, s=s)
+    t = r + t0 + 22.5 * s + extra
+    c = t0 + 8.5 * s
+    with mp.workdps(30):
+        f = lambda x: mp.exp(-(x - c) ** 2 / (2 * s * s)) * mp.sin(w * (x - c)) / mp.sqrt((t - x) ** 2 - r * r)
+        pts = [t0] + [c + k * s / 4 for k in range(-33, 57)] + [t0 + 22.5 * s, t0 + 24 * s]
+        val = float(mp.quad(f, pts))
+        tail = float(mp.quad(f, [t0 + 14 * s + k * s / 4 for k in range(0, 35)]))
+    u = u1((0.0, 0.0), (r, 0.0), t, sig)
+    assert abs(val) > 1e-6
+    assert u == pytest.approx(val / (2 * math.pi), rel=1e-12, abs=1e-18)
+    assert abs(tail) > 1e-9 * abs(val)
