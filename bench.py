@@ -20,6 +20,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -44,28 +45,42 @@ def kernels_digest() -> str:
     return hashlib.sha256("\n".join(l for l in code if l.strip()).encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` (read + written) from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, scaled by its copy-kernel calibration; None when the
-    summary is missing, does not list the kernel, or was taken on other kernel code."""
-    import re
-    path = os.path.join(ROOT, "profiles", "hbm_counters_cfg4_M1e6_mixed.md")
+def traffic_summary_path(precision: str) -> str:
+    return os.path.join(ROOT, "profiles", f"hbm_counters_cfg4_M1e6_{precision}.md")
+
+
+def kernel_row_matches(name: str, base: str, targs) -> bool:
+    """True when the rocprofv3 kernel name `name` (e.g. ``wfp2d::k_near<float>``) is kernel
+    `base` whose leading template arguments are `targs` (strings; () = any)."""
+    m = re.fullmatch(r"(?:wfp2d::)?(\w+)(?:<(.*)>)?", name.strip())
+    if not m or m.group(1) != base:
+        return False
+    args = [a.strip() for a in (m.group(2) or "").split(",")] if m.group(2) else []
+    return list(args[:len(targs)]) == [str(t) for t in targs]
+
+
+def measured_traffic(base: str, targs=(), precision: str = "mixed"):
+    """HBM bytes per launch (read + written) of kernel `base`<targs...> from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary of that precision, scaled by its copy-kernel
+    calibration; None when the summary is missing, lists no such instantiation (exactly one
+    must match), or was taken on other kernel code."""
     try:
-        text = open(path).read()
+        text = open(traffic_summary_path(precision)).read()
         digest = kernels_digest()
     except OSError:
         return None
     m = re.search(r"code sha256 prefix: ([0-9a-f]{16})", text)
     if not m or m.group(1) != digest:
         return None
+    hits = []
     for line in text.splitlines():
         cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
-        if len(cells) == 4 and cells[0].split("<")[0].endswith(kernel):
+        if len(cells) == 4 and kernel_row_matches(cells[0], base, targs):
             try:
-                return int(round((float(cells[2]) + float(cells[3])) * 1e6))
+                hits.append(int(round((float(cells[2]) + float(cells[3])) * 1e6)))
             except ValueError:
                 return None
-    return None
+    return hits[0] if len(hits) == 1 else None
 
 
 def copy_bandwidth(dev, gib: float = 1.0, reps: int = 5) -> float:
@@ -88,12 +103,63 @@ def copy_bandwidth(dev, gib: float = 1.0, reps: int = 5) -> float:
     return bw
 
 
+def n_max(info: dict) -> int:
+    """Sigma levels per pair in the paper's local sum (Sec. 6): W + 1 + ceil(p/2)."""
+    return info["W"] + 1 + (info["p"] + 1) // 2
+
+
+def local_impl_flops(info: dict) -> int:
+    """FP64 flops of the local kernel as executed: per source, the Chebyshev profile on every
+    regular sub-panel (each coefficient a dot product over the sigma levels); per pair, one
+    Clenshaw evaluation (2 flops per term) plus distance and sub-panel coordinate (~12 flops)."""
+    return (2 * info["M"] * info["n_regular_subpanels"] * info["cheb_degree"] * info["n_levels"]
+            + info["n_local_pairs"] * (2 * info["cheb_degree"] + 12))
+
+
+def stage_kernel(stage: str, info: dict):
+    """(kernel base name, leading template arguments) of the kernel a stage launches."""
+    r = "float" if info["precision"] == 1 else "double"
+    table = {"ingest": ("k_ingest", ()), "spread": ("k_spread", (r,)), "fft_rows1": ("k_fft_t1", (r, 0)),
+             "fft_cols1": ("k_fft_t1", (r, 1)), "split": ("k_split", (r,)), "near": ("k_near", (r,)),
+             "far": ("k_far", (r,)), "fft_cols2": ("k_fft_t2", (r, 0)), "fft_rows2": ("k_fft_t2", (r, 1)),
+             "interp": ("k_interp", (r,)), "combine": ("k_combine", ())}
+    if stage == "local":
+        path = info["local_path"]
+        if path == 2:
+            return "k_local_pairs", (info["n_levels"], info["cheb_degree"])
+        return ("k_local_fast", (info["n_levels"],)) if path == 1 else ("k_local", ())
+    return table[stage]
+
+
+def golden_samples(name: str):
+    """{(target, step): u} of the stored oracle samples of a workload, or {} when none are
+    committed (tests/golden/<workload>_oracle_samples.txt, written by the script beside it)."""
+    path = os.path.join(ROOT, "tests", "golden", name.split("_")[0] + "_oracle_samples.txt")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        i, n, v = line.split()
+        out[(int(i), int(n))] = float(v)
+    return out
+
+
+def timed_window(nt: int, LA: int, W: int, K: int):
+    """First and last reported step of the timed window: the window ends at the workload's
+    last step nt (extended past it when K steps would reach back before the far history
+    starts), so every timed step has the far history active."""
+    last = max(nt, LA + W + 1 + K)
+    return last - K + 1, last
+
+
 def stage_costs(info: dict) -> dict:
     """Algorithmic work of one launch of each stage: (bound, amount, unit).
 
     HBM-bound stages count the bytes a launch must move at least once
     (reads + writes of its inputs, state and outputs); the local part counts
-    FP64 flops (table evaluation plus contraction per source-target pair).
+    the method's FP64 flops (2 per source-target pair and sigma level).
     """
     c = 4 if info["precision"] == 1 else 8          # bytes per real in the grid/FFT/ring precision
     H, W = info["n_modes"], info["W"]
@@ -112,11 +178,9 @@ def stage_costs(info: dict) -> dict:
         "fft_cols2": ("hbm", H * 2 * c + (R + 1) * Lp * 2 * c),
         "fft_rows2": ("hbm", (R + 1) * Lp * 2 * c + Lp * Lp * c),
         "interp": ("hbm", Lp * Lp * c + Nx * (8 + 2 * w * c + 8)),
-        # FP64 flops of the algorithm as executed: per source, the Chebyshev profile on every regular
-        # sub-panel (D coefficients, each a dot product over the sigma levels); per pair, one Clenshaw
-        # evaluation of degree D (2 flops per term) plus distance and sub-panel coordinate (~12 flops)
-        "local": ("alu", 2 * M * info["n_regular_subpanels"] * info["cheb_degree"] * nlev
-                  + info["n_local_pairs"] * (2 * info["cheb_degree"] + 12)),
+        # the method's FP64 work (Sec. 6, eq. local2 after eq. sigInterp): one multiply-add per
+        # source-target pair and sigma level, n_max = W + 1 + ceil(p/2) levels per pair
+        "local": ("alu", 2 * info["n_local_pairs"] * n_max(info)),
         "combine": ("hbm", Nx * (8 + 8 + 4 + 8)),
     }
     return cost
@@ -294,15 +358,176 @@ def batch_bench(args, log):
         p.close()
 
 
+def run_form(args, w, precision: str, dev, log, golden: dict) -> dict:
+    """Time K whole steps of one plan over the workload's fixed window and check them.
+
+    The plan is pre-rolled (steps only: evaluation keeps no state) up to the window, then
+    runs `warmup` untimed step+evaluate pairs, then K timed ones.  Reported steps are
+    first..last (ingested steps first + lookahead .. last + lookahead)."""
+    import torch
+    import paper_2604_07170_amd as pa
+
+    K, Wu = args.steps, args.warmup
+    t0 = time.time()
+    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=precision, interp_order=w.p,
+                    lookahead=args.lookahead, max_steps=max(w.nt, 1) + K + 64)
+    info = plan.info()
+    init_s = time.time() - t0
+    L = info["lookahead"]
+    first, last = timed_window(w.nt, info["LA"], info["W"], K)
+    n_first = first + L                                   # first timed ingested step
+    Wu = min(Wu, n_first - 1)
+    log(f"[bench] {w.name} {precision}: plan ready in {init_s:.1f}s  modes={info['n_modes']} nf={info['nf']} "
+        f"band={info['band']} pairs={info['n_local_pairs']} lookahead={L} HBM={info['bytes_device'] / 2**30:.1f}GiB; "
+        f"timed steps report u(t_{first}..t_{last})")
+    params = w.torch_params(dev)
+    tuning = None
+    if not args.no_autotune:
+        from paper_2604_07170_amd.autotune import tune_spread
+        tuning = tune_spread(plan)
+        log(f"[bench] spreading tile {tuning['tile']} ({tuning['class']}): {tuning['ms']}")
+    u_last = torch.empty(w.Nx, dtype=torch.float64, device=dev)
+
+    # ---- pre-roll to the window, then the untimed warm-up steps ----
+    t0 = time.time()
+    for n in range(1, n_first):
+        plan.step(w.sigma_torch(n * w.dt, dev, params))
+        if n >= n_first - Wu:
+            plan.evaluate(u_last)
+        if n % 1000 == 0:
+            torch.cuda.synchronize()
+            log(f"[bench] pre-roll step {n}/{n_first - 1} ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+
+    # ---- inputs of the timed steps, resident in HBM before timing; one output row per step ----
+    sig = torch.empty((K, w.M), dtype=torch.float64, device=dev)
+    for k in range(K):
+        sig[k] = w.sigma_torch((n_first + k) * w.dt, dev, params)
+    nonzero = int((sig.abs().amax(dim=1) > 0).sum())
+    if nonzero < K:
+        raise SystemExit(f"bench: {K - nonzero} of the {K} timed steps have sigma == 0 everywhere")
+    u_out = torch.empty((K, w.Nx), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K whole steps, HIP events on the plan's stream ----
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(K):
+        plan.step(sig[k])
+        plan.evaluate(u_out[k])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    elapsed_ms = ev0.elapsed_time(ev1)
+    stages = plan.get_timing()
+    plan.set_timing(False)
+    assert plan.info()["step_reported"] == last
+    ms_per_step = elapsed_ms / K
+    log(f"[bench] {precision}: timed {K} steps: {elapsed_ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
+        f"{ms_per_step:.3f} ms/step")
+
+    # ---- per-stage roofline ----
+    costs = stage_costs(info)
+    per_stage = {}
+    for s, (ms, n) in stages.items():
+        if n == 0:
+            continue
+        bound, amt = costs[s]
+        avg_ms = ms / n
+        if bound == "hbm":
+            ach = amt / (avg_ms * 1e-3) / 1e9
+            per_stage[s] = dict(avg_ms=round(avg_ms, 5), bound="hbm", achieved_GBs=round(ach, 1),
+                                frac=round(ach / PEAK_HBM_GBS, 4), bytes=int(amt))
+        else:
+            ach = amt / (avg_ms * 1e-3) / 1e12
+            impl = local_impl_flops(info)
+            per_stage[s] = dict(avg_ms=round(avg_ms, 5), bound="alu", achieved_TFLOPs=round(ach, 3),
+                                frac=round(ach / PEAK_FP64_TFLOPS, 4), flops=int(amt), impl_flops=int(impl),
+                                impl_TFLOPs=round(impl / (avg_ms * 1e-3) / 1e12, 3))
+    hbm_bytes = sum(costs[s][1] for s in per_stage if costs[s][0] == "hbm")
+
+    # ---- parity inside the window: stored oracle samples at the timed steps ----
+    checks = sorted({n for (_, n) in golden if first <= n <= last})
+    got, ref = [], []
+    for n in checks:
+        idx = sorted(i for (i, m) in golden if m == n)
+        row = u_out[n - first].index_select(0, torch.as_tensor(idx, device=dev)).cpu().numpy()
+        got.extend(row.tolist())
+        ref.extend(golden[(i, n)] for i in idx)
+    stored = None
+    if ref:
+        got, ref = np.array(got), np.array(ref)
+        if not np.linalg.norm(ref) > 0:
+            raise SystemExit("bench: the stored oracle samples of the window are all zero")
+        stored = {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), "samples": int(ref.size),
+                  "steps": checks}
+        log(f"[bench] {precision}: {ref.size} stored oracle samples at steps {checks}: rel L2 {stored['rel_l2']:.2e}")
+    res = dict(plan=plan, info=info, init_s=init_s, first=first, last=last, K=K, warmup=Wu,
+               elapsed_ms=elapsed_ms, ms_per_step=ms_per_step, per_stage=per_stage, hbm_bytes=hbm_bytes,
+               stored=stored, u_last=u_out[K - 1].clone(), tuning=tuning)
+    del u_out, sig
+    return res
+
+
+def cpu_oracle_sample(args, w, info, step: int, u_gpu, log):
+    """Time the CPU oracle at `step` on a seeded sample of targets (all M sources each) and
+    compare the GPU field there; the rate extrapolates the sample to all Nx targets."""
+    import oracle
+    rng = np.random.default_rng(77)
+    ti = np.sort(rng.choice(w.Nx, size=args.cpu_sample_targets, replace=False))
+    nth = oracle.threads()
+    c0 = time.perf_counter()
+    u_ref = oracle.u_workload(w, ti, [step * w.dt], self_mode=1, delta=info["delta"], b=info["b"])[:, 0]
+    t_cpu = time.perf_counter() - c0
+    if not np.linalg.norm(u_ref) > 0:
+        raise SystemExit(f"bench: the oracle field at step {step} is zero at the sampled targets")
+    rate = w.M * len(ti) / (t_cpu * w.Nx)
+    cpu = {"value": rate, "unit": "source*steps/s", "cores": nth, "kind": "oracle",
+           "sample": f"{len(ti)} seeded target(s) x 1 step (t_{step}, far history active) x all {w.M} "
+                     f"sources, {t_cpu:.1f} s on {nth} threads; rate = M * samples / (t_sample * Nx)"}
+    err = float(np.linalg.norm(u_gpu[ti] - u_ref) / np.linalg.norm(u_ref))
+    log(f"[bench] oracle sample at step {step}: {t_cpu:.1f}s on {nth} threads; GPU vs oracle rel err {err:.2e}")
+    return cpu, err, ti, u_ref
+
+
+def roofline_of(res, precision):
+    per_stage, info = res["per_stage"], res["info"]
+    dom = max(per_stage, key=lambda s: per_stage[s]["avg_ms"])
+    d = per_stage[dom]
+    base, targs = stage_kernel(dom, info)
+    kname = base + ("<" + ", ".join(str(t) for t in targs) + ">" if targs else "")
+    if d["bound"] == "hbm":
+        roof = {"bound": "hbm", "kernel": kname, "achieved": d["achieved_GBs"], "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": d["frac"]}
+    else:
+        roof = {"bound": "alu", "kernel": kname, "achieved": d["achieved_TFLOPs"], "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": d["frac"], "work": "2 FP64 flops per source-target pair and sigma "
+                "level, n_max = W + 1 + ceil(p/2) levels (the method's count)",
+                "impl_TFLOPs": d["impl_TFLOPs"]}
+    roof["traffic"] = measured_traffic(base, targs, precision)
+    roof["avg_ms"] = d["avg_ms"]
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5800)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed step+evaluate iterations just before the timed window (the plan is "
+                         "pre-rolled to the window regardless)")
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--forms", default="mixed,fp64",
+                    help="comma list of precisions to time; the first gives the headline value")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default=None,
+                    help="shorthand for --forms with one precision (also the adjoint / batch precision)")
+    ap.add_argument("--lookahead", type=int, default=-1, help="reporting delay of the plan (-1 = its default)")
     ap.add_argument("--cpu-sample-targets", type=int, default=1,
-                    help="targets of the CPU oracle sample (at the last timed step)")
+                    help="targets of the timed CPU oracle sample (at the last timed step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default spreading tile shape")
     ap.add_argument("--adjoint", action="store_true",
@@ -316,6 +541,12 @@ def main():
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a device-to-device copy of this many GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.precision is not None:
+        args.forms = args.precision
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    if not forms or any(f not in ("mixed", "fp64") for f in forms):
+        raise SystemExit("--forms takes mixed and/or fp64")
+    args.precision = forms[0]
 
     if args.copy_probe_gib > 0:
         import torch
@@ -332,9 +563,10 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only: the sharding of the method over "
                                    "several GPUs is not built", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        raise SystemExit("--steps must be >= 1 and --warmup >= 0")
 
     import torch
-    import paper_2604_07170_amd as pa
     from wfp_workloads import config
 
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
@@ -347,146 +579,85 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     w = config(args.config)
-    copy_gbs = copy_bandwidth(dev)            # before the plan takes its memory
+    golden = golden_samples(w.name)
+    copy_gbs = copy_bandwidth(dev)            # before the plans take their memory
     log(f"[bench] device copy: {copy_gbs:.0f} GB/s (read + write)")
-    t0 = time.time()
-    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=args.precision, interp_order=w.p,
-                    max_steps=args.warmup + args.steps + 32)
-    info = plan.info()
-    init_s = time.time() - t0
-    L = info["lookahead"]
-    log(f"[bench] {w.name}: plan ready in {init_s:.1f}s  modes={info['n_modes']} nf={info['nf']} "
-        f"band={info['band']} pairs={info['n_local_pairs']} lookahead={L} HBM={info['bytes_device'] / 2**30:.1f}GiB")
-    params = w.torch_params(dev)
-    u = torch.empty(w.Nx, dtype=torch.float64, device=dev)
-    tuning = None
-    if not args.no_autotune:
-        from paper_2604_07170_amd.autotune import tune_spread
-        tuning = tune_spread(plan)
-        log(f"[bench] spreading tile {tuning['tile']} ({tuning['class']}): {tuning['ms']}")
 
-    # ---- warm-up: the full pipeline, so the timed window starts at step warmup+1 ----
-    t0 = time.time()
-    nw = args.warmup
-    for n in range(1, nw + 1):
-        plan.step(w.sigma_torch(n * w.dt, dev, params))
-        if n > nw - 3:
-            plan.evaluate(u)
-        if n % 500 == 0:
-            torch.cuda.synchronize()
-            log(f"[bench] warm-up step {n}/{nw} ({time.time() - t0:.1f}s)")
-    torch.cuda.synchronize()
+    results = {}
+    cpu, live_err = None, {}
+    for f in forms:
+        res = run_form(args, w, f, dev, log, golden)
+        if f == forms[0] and not args.no_cpu_baseline:
+            u_gpu = res["u_last"].cpu().numpy()
+            cpu, live_err[f], live_idx, live_ref = cpu_oracle_sample(args, w, res["info"], res["last"], u_gpu, log)
+            live_step = res["last"]
+        elif cpu is not None and res["last"] == live_step:
+            # every form reports the same steps: compare with the oracle values already computed
+            u_gpu = res["u_last"].cpu().numpy()[live_idx]
+            live_err[f] = float(np.linalg.norm(u_gpu - live_ref) / np.linalg.norm(live_ref))
+        res["plan"].close()
+        del res["plan"], res["u_last"]
+        torch.cuda.empty_cache()
+        results[f] = res
 
-    # ---- inputs of the timed steps, resident in HBM before timing ----
-    K = args.steps
-    sig = torch.empty((K, w.M), dtype=torch.float64, device=dev)
-    for k in range(K):
-        sig[k] = w.sigma_torch((nw + 1 + k) * w.dt, dev, params)
-    torch.cuda.synchronize()
+    def summary(f):
+        r = results[f]
+        return {"value": w.M * r["K"] / (r["elapsed_ms"] / 1e3), "ms_per_step": r["ms_per_step"],
+                "roofline": roofline_of(r, f),
+                "hbm_roofline_step_frac": round(r["hbm_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                "sample_rel_err_vs_oracle": r["stored"]["rel_l2"] if r["stored"] else live_err.get(f),
+                "stored_oracle_check": r["stored"], "live_oracle_rel_err": live_err.get(f),
+                "plan_init_s": round(r["init_s"], 2), "stages": r["per_stage"]}
 
-    # ---- timed region: K whole steps, HIP events on the plan's stream ----
-    stream = torch.cuda.current_stream(dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    plan.set_timing(True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    for k in range(K):
-        plan.step(sig[k])
-        plan.evaluate(u)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    elapsed_ms = ev0.elapsed_time(ev1)
-    stages = plan.get_timing()
-    plan.set_timing(False)
-    step_reported = plan.info()["step_reported"]
-    ms_per_step = elapsed_ms / K
-    value = w.M * K / (elapsed_ms / 1e3)
-    log(f"[bench] timed {K} steps: {elapsed_ms:.1f} ms (wall {wall * 1e3:.1f} ms), {ms_per_step:.3f} ms/step")
-
-    # ---- roofline of the dominant kernel ----
-    costs = stage_costs(info)
-    per_stage = {}
-    for s, (ms, n) in stages.items():
-        if n == 0:
-            continue
-        bound, amt = costs[s]
-        avg_ms = ms / n
-        if bound == "hbm":
-            ach = amt / (avg_ms * 1e-3) / 1e9
-            per_stage[s] = dict(avg_ms=round(avg_ms, 5), bound="hbm", achieved_GBs=round(ach, 1),
-                                frac=round(ach / PEAK_HBM_GBS, 4), bytes=int(amt))
-        else:
-            ach = amt / (avg_ms * 1e-3) / 1e12
-            per_stage[s] = dict(avg_ms=round(avg_ms, 5), bound="alu", achieved_TFLOPs=round(ach, 3),
-                                frac=round(ach / PEAK_FP64_TFLOPS, 4), flops=int(amt))
-    dom = max(per_stage, key=lambda s: per_stage[s]["avg_ms"])
-    d = per_stage[dom]
-    if d["bound"] == "hbm":
-        roof = {"bound": "hbm", "kernel": pa.Wfp2d.KERNELS[pa.Wfp2d.STAGES.index(dom)], "achieved": d["achieved_GBs"],
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": d["frac"], "traffic": None}
-        roof["traffic"] = measured_traffic(roof["kernel"])
-    else:
-        roof = {"bound": "alu", "kernel": pa.Wfp2d.KERNELS[pa.Wfp2d.STAGES.index(dom)], "achieved": d["achieved_TFLOPs"],
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": d["frac"], "traffic": None}
-        if roof["kernel"] == "k_local":          # the local-part kernel the plan runs
-            roof["kernel"] = ["k_local", "k_local_fast", "k_local_pairs"][info["local_path"]]
-        roof["traffic"] = measured_traffic(roof["kernel"])
-    hbm_bytes = sum(costs[s][1] for s in per_stage if costs[s][0] == "hbm")
-    step_hbm_frac = hbm_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS
-
-    # ---- CPU oracle on a bounded sample (+ a full-scale parity check of that sample) ----
-    cpu = None
-    sample_err = None
-    if not args.no_cpu_baseline:
-        import oracle
-        rng = np.random.default_rng(77)
-        ti = rng.choice(w.Nx, size=args.cpu_sample_targets, replace=False)
-        t_rep = step_reported * w.dt
-        u_gpu = u.cpu().numpy()[ti]
-        nth = oracle.threads()
-        c0 = time.perf_counter()
-        u_ref = oracle.u_workload(w, ti, [t_rep], self_mode=1, delta=info["delta"], b=info["b"])[:, 0]
-        t_cpu = time.perf_counter() - c0
-        # the full job (all Nx targets x K steps) would take t_cpu * Nx * K / n_samples
-        rate = w.M * len(ti) / (t_cpu * w.Nx)
-        cpu = {"value": rate, "unit": "source*steps/s", "cores": nth, "kind": "oracle",
-               "sample": f"{len(ti)} seeded target(s) x 1 step (t_{step_reported}) x all {w.M} sources, "
-                         f"{t_cpu:.1f} s; rate = M * samples / (t_sample * Nx)"}
-        sample_err = float(np.linalg.norm(u_gpu - u_ref) / max(np.linalg.norm(u_ref), 1e-300))
-        log(f"[bench] oracle sample {t_cpu:.1f}s on {nth} threads; GPU vs oracle rel err {sample_err:.2e}")
-
+    head_f = forms[0]
+    h = results[head_f]
+    hs = summary(head_f)
+    info = h["info"]
     out = {
         "metric": "source\u00b7timesteps/sec at 1e-6 rel L2 error; % of HBM roofline (mixed vs FP64)",
-        "value": value,
+        "value": hs["value"],
         "unit": "source*steps/s",
         "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "steps": h["K"],
+        "warmup": h["warmup"],
+        "ms_per_step": hs["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "dtype": "f32+f64" if head_f == "mixed" else "f64",
         "data": "synthetic (seeded closed-form signatures, random sources)",
         "config": {"workload": w.name, "M": w.M, "Nx": w.Nx, "dt": w.dt, "W": w.W, "p": w.p, "eps": w.tol,
-                   "timed_steps": f"{args.warmup + 1}..{args.warmup + K} (reported u at t_{step_reported - K + 1}.."
-                                  f"t_{step_reported})", "precision": args.precision,
+                   "timed_steps": f"{h['first'] + info['lookahead']}..{h['last'] + info['lookahead']} ingested, "
+                                  f"reporting u(t_{h['first']})..u(t_{h['last']}) (far history active from step "
+                                  f"{info['LA'] + info['W']}); pre-rolled to the window, then {h['warmup']} "
+                                  f"untimed warm-up steps",
+                   "precision": head_f, "lookahead": info["lookahead"],
                    "n_modes": info["n_modes"], "nf": info["nf"], "local_pairs": info["n_local_pairs"],
-                   "spread_tile": list(pa.Wfp2d.SPREAD_TILES[plan.info()["spread_tile"]]),
+                   "spread_tile": list(h["tuning"]["tile"]) if h["tuning"] else None,
                    "local_path": ["generic", "pair search", "pair lists"][info["local_path"]],
                    "cheb_terms": info["cheb_degree"]},
-        "roofline": roof,
-        "hbm_roofline_step_frac": round(step_hbm_frac, 4),
+        "roofline": hs["roofline"],
+        "hbm_roofline_step_frac": hs["hbm_roofline_step_frac"],
         "hbm_copy_GBs": round(copy_gbs, 1),
-        "plan_init_s": round(init_s, 2),
-        "stages": per_stage,
+        "plan_init_s": hs["plan_init_s"],
+        "stages": hs["stages"],
         "cpu_baseline": cpu,
-        "sample_rel_err_vs_oracle": sample_err,
+        "sample_rel_err_vs_oracle": hs["sample_rel_err_vs_oracle"],
+        "stored_oracle_check": hs["stored_oracle_check"],
+        "live_oracle_rel_err": hs["live_oracle_rel_err"],
     }
+    for f in forms[1:]:
+        s = summary(f)
+        out[f] = {k: s[k] for k in ("value", "ms_per_step", "roofline", "hbm_roofline_step_frac",
+                                    "sample_rel_err_vs_oracle", "stored_oracle_check", "live_oracle_rel_err",
+                                    "plan_init_s", "stages")}
+        out[f"{head_f}_over_{f}"] = round(hs["value"] / s["value"], 3)
+    errs = [e for e in [hs["sample_rel_err_vs_oracle"]] + [out[f]["sample_rel_err_vs_oracle"] for f in forms[1:]]
+            if e is not None]
     print(json.dumps(out), flush=True)
-    plan.close()
+    if errs and max(errs) > 1e-6:
+        log(f"[bench] WARNING: oracle check above 1e-6 ({max(errs):.2e})")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -49,3 +49,29 @@ def test_comment_edits_keep_and_code_edits_drop_the_counters(tree):
 def test_missing_summary_gives_no_traffic(tree):
     os.remove(tree.parents[2] / "profiles" / "hbm_counters_cfg4_M1e6_mixed.md")
     assert bench.measured_traffic("k_local_pairs") is None
+
+
+def test_lookup_is_keyed_by_precision_and_template(tree):
+    assert bench.measured_traffic("k_near", ("float",), "mixed") is not None
+    assert bench.measured_traffic("k_near", ("double",), "mixed") is None      # an FP64 kernel: not profiled
+    assert bench.measured_traffic("k_near", ("float",), "fp64") is None        # no FP64 summary here
+    assert bench.measured_traffic("k_local_pairs", (35, 16), "mixed") is not None
+    assert bench.measured_traffic("k_local_pairs", (35, 20), "mixed") is None
+    # several instantiations match a bare base name: ambiguous, so no figure
+    assert bench.measured_traffic("k_fft_t1", (), "mixed") is None
+    assert bench.measured_traffic("k_fft_t1", ("float", 1), "mixed") is not None
+
+
+def test_kernel_row_names():
+    assert bench.kernel_row_matches("wfp2d::k_local_pairs<35, 16, 512>", "k_local_pairs", (35, 16))
+    assert not bench.kernel_row_matches("wfp2d::k_local_pairs<35, 16, 512>", "k_local", ())
+    assert bench.kernel_row_matches("wfp2d::k_combine", "k_combine", ())
+    assert not bench.kernel_row_matches("wfp2d::k_combine_dot", "k_combine", ())
+
+
+def test_timed_window_ends_at_the_last_step_after_far_onset():
+    # 10^6-source workload: nt = 6000, LA = 4300, W = 16
+    assert bench.timed_window(6000, 4300, 16, 200) == (5801, 6000)
+    assert bench.timed_window(6000, 4300, 16, 20) == (5981, 6000)
+    first, last = bench.timed_window(6000, 4300, 16, 3000)
+    assert first > 4300 + 16 and last - first + 1 == 3000

@@ -64,24 +64,34 @@ class Workload:
         if params is None:
             params = self.torch_params(device)
         fam, amp, t0, om, s = params
+        present = self._families_present()
         t = torch.as_tensor(float(t), dtype=torch.float64, device=device)
         out = torch.zeros_like(amp)
         g = fam == FAMILY_G
-        if bool(g.any()):
+        if present[FAMILY_G]:
             c = t0 + 8.5 * s
             v = amp * torch.exp(-((t - c) ** 2) / (2 * s * s)) * torch.sin(om * (t - c))
             out = torch.where(g & (t > t0), v, out)
         e = fam == FAMILY_E
-        if bool(e.any()):
+        if present[FAMILY_E]:
             v = amp * 0.5 * (torch.erf(5.0 * (t - t0)) + 1.0) * torch.sin(om * (t - t0))
             out = torch.where(e & (t > 0), v, out)
         st = fam == FAMILY_STEP
-        if bool(st.any()):
+        if present[FAMILY_STEP]:
             out = torch.where(st & (t > t0), amp, out)
         rp = fam == FAMILY_RAMP
-        if bool(rp.any()):
+        if present[FAMILY_RAMP]:
             out = torch.where(rp & (t > t0), amp * (t - t0), out)
         return out
+
+    def _families_present(self):
+        """Which signature families occur (host-side, so evaluating on a device never waits)."""
+        key = (id(self.family), self.family.shape)
+        cached = self.__dict__.get("_present")
+        if cached is None or cached[0] != key:
+            cached = (key, [bool(np.any(self.family == f)) for f in range(4)])
+            self.__dict__["_present"] = cached
+        return cached[1]
 
     def torch_params(self, device):
         import torch
