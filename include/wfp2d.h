@@ -159,6 +159,28 @@ wfp2d_status wfp2d_step(wfp2d_plan plan, const double *sigma);
  */
 wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as wfp2d_evaluate (same kernels, same result up to the order of
+ * floating-point sums), but its transient buffers (the type-2 FFT
+ * intermediates, the real fine grid, u_h and u_l) are taken from a fixed
+ * 64 MiB device workspace instead of the plan's own.  It allocates and frees
+ * nothing.  The workspace is one static array per device, mapped when the
+ * library is loaded, located at wfp2d_init and held until the process ends;
+ * every plan on that device shares it and it keeps the last call's contents
+ * (nothing in it has to start at zero).  Calls on one device that may run at
+ * the same time (on different streams or host threads) race; calls ordered
+ * on one stream do not.  A plan whose evaluation needs more than 64 MiB
+ * (2 (R+1) band + band^2 reals plus 16 Nx bytes, each buffer rounded up to
+ * 256 bytes) is rejected with ERR_ARG.  wfp2d_debug_copy(4 / 5) shows the
+ * plan's own buffers, written by wfp2d_evaluate only.
+ * u: device pointer [Nx] float64, as for wfp2d_evaluate.
+ * Errors: ERR_ARG (NULL u, workspace too small), ERR_STATE (stage timing
+ * enabled), ERR_DEVICE.
+ */
+wfp2d_status wfp2d_evaluate_noalloc(wfp2d_plan plan, double *u);
+
 /* Derived parameters and sizes of a plan.  Errors: ERR_ARG. */
 wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info);
 

@@ -88,6 +88,7 @@ def load_library():
     lib.wfp2d_batch_launch.argtypes = [vp]
     lib.wfp2d_batch_destroy.argtypes = [vp]
     lib.wfp2d_evaluate_dot.argtypes = [vp, vp, vp]
+    lib.wfp2d_evaluate_noalloc.argtypes = [vp, vp]
     lib.wfp2d_adjoint_init.argtypes = [ctypes.POINTER(vp), vp]
     lib.wfp2d_state_bytes.argtypes = [vp, ctypes.POINTER(i64)]
     lib.wfp2d_reset.argtypes = [vp]
@@ -99,7 +100,8 @@ def load_library():
               "wfp2d_debug_copy", "wfp2d_host_eval", "wfp2d_set_timing", "wfp2d_get_timing", "wfp2d_graph_capture",
               "wfp2d_graph_launch", "wfp2d_batch_create", "wfp2d_batch_launch", "wfp2d_batch_destroy",
               "wfp2d_set_spread_tile", "wfp2d_time_spread", "wfp2d_evaluate_dot", "wfp2d_adjoint_init",
-              "wfp2d_state_bytes", "wfp2d_save_state", "wfp2d_load_state", "wfp2d_reset"):
+              "wfp2d_state_bytes", "wfp2d_save_state", "wfp2d_load_state", "wfp2d_reset",
+              "wfp2d_evaluate_noalloc"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -213,6 +215,15 @@ class Wfp2d:
         if not (out.is_cuda and out.dtype == t.float64 and out.numel() == self.Nx and out.is_contiguous()):
             raise ValueError("out must be a contiguous float64 CUDA tensor with Nx elements")
         self._check(self.lib.wfp2d_evaluate(self.h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def evaluate_noalloc(self, out):
+        """wfp2d_evaluate_noalloc: evaluate into `out` with the library's fixed device workspace."""
+        t = self._torch
+        if not (isinstance(out, t.Tensor) and out.is_cuda and out.dtype == t.float64 and out.numel() == self.Nx
+                and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 CUDA tensor with Nx elements")
+        self._check(self.lib.wfp2d_evaluate_noalloc(self.h, ctypes.c_void_p(out.data_ptr())))
         return out
 
     def evaluate_dot(self, weights, acc):

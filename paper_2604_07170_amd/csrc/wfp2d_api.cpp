@@ -281,6 +281,7 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
 static void build(Plan &p, const double *src_xy, const double *tgt_xy)
 {
     hip_check(hipSetDevice(p.device), "hipSetDevice");
+    hip_check(scratch_address(p.device, &p.scratch), "hipGetSymbolAddress of the fixed workspace");
     {
         int ncu = 0;
         hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device), "hipDeviceGetAttribute");
@@ -869,6 +870,42 @@ wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u)
     WFP2D_GUARD(plan, {
         if (!u) fail(WFP2D_ERR_ARG, "NULL u");
         do_evaluate(plan->p, u);
+    });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_evaluate_noalloc(wfp2d_plan plan, double *u)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, {
+        Plan &p = plan->p;
+        if (!u) fail(WFP2D_ERR_ARG, "NULL u");
+        if (p.timing) fail(WFP2D_ERR_STATE, "stage timing is enabled");
+        if (!p.scratch) fail(WFP2D_ERR_STATE, "no fixed workspace address for this device");
+        // the evaluation's transient buffers, carved from the fixed workspace on 256-byte boundaries
+        auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t t2 = up((size_t)(p.g.R + 1) * p.g.Lpad * 2 * p.sizeof_real);
+        const size_t cg = up((size_t)p.g.Lpad * p.g.Lpad * p.sizeof_real);
+        const size_t uv = up((size_t)p.Nx * sizeof(double));
+        const size_t need = 2 * t2 + cg + 2 * uv;
+        if (need > kScratchBytes)
+            fail(WFP2D_ERR_ARG, "evaluation workspace of " + std::to_string(need) + " bytes exceeds the fixed " +
+                                    std::to_string(kScratchBytes) + "-byte workspace (use wfp2d_evaluate)");
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        char *base = (char *)p.scratch;
+        void *own[5] = {p.d_T2, p.d_T2t, p.d_cgrid, p.d_uh, p.d_ul};
+        p.d_T2 = base;
+        p.d_T2t = base + t2;
+        p.d_cgrid = base + 2 * t2;
+        p.d_uh = (double *)(base + 2 * t2 + cg);
+        p.d_ul = (double *)(base + 2 * t2 + cg + uv);
+        try {
+            enqueue_evaluate(p, u);   // each buffer is written in full before it is read (u_l by a fill kernel)
+        } catch (...) {
+            p.d_T2 = own[0], p.d_T2t = own[1], p.d_cgrid = own[2], p.d_uh = (double *)own[3], p.d_ul = (double *)own[4];
+            throw;
+        }
+        p.d_T2 = own[0], p.d_T2t = own[1], p.d_cgrid = own[2], p.d_uh = (double *)own[3], p.d_ul = (double *)own[4];
     });
     return WFP2D_OK;
 }

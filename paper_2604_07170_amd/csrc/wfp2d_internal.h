@@ -33,6 +33,8 @@ constexpr int kPairThreads = 1024; //   threads per workgroup: 16 waves, one wor
 constexpr int kPairThreadsHalf = 512; //   8 waves, two per CU, when the rows fit 8 x kPairRB blocks
 constexpr int kPairRB = 2;         //   16-row blocks of the coefficient table per wave
 constexpr int kFastOwn = 4;        //   targets owned per thread
+// fixed device workspace of wfp2d_evaluate_noalloc (one per device, held until the process ends)
+constexpr size_t kScratchBytes = size_t(64) << 20;
 
 // Work chunk of a per-mode kernel: modes [off, off+cnt) of packed column nx,
 // whose first mode has ny = ny0 (ny increases by one per mode).
@@ -81,6 +83,9 @@ hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt);
 hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n);
 hipError_t launch_combine_dot(Plan &p, const double *wts, double *acc);
 hipError_t launch_combine(Plan &p, double *u_out);
+// Device address of the fixed workspace on `device` (which must be current): looked up once per
+// device with hipGetSymbolAddress and kept; later calls return the kept address.
+hipError_t scratch_address(int device, void **out);
 
 // ---- the plan ----
 struct Plan {
@@ -181,6 +186,7 @@ struct Plan {
     int64_t *d_seg_off = nullptr, *d_seg_doff = nullptr;     // first pair of each segment, [n_seg + 1]
     double *d_pair_dw = nullptr;      // eta_d(r) of each pair with r < dt/2, [n_dy_pairs][nlev]
     int32_t n_cu = 256;               // compute units of the device (persistent grids)
+    void *scratch = nullptr;          // this device's fixed workspace (see scratch_address)
     uint64_t *d_pair_pw = nullptr;    // regular pairs, one packed word each
     uint32_t *d_pair_dent = nullptr;
 

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "wfp2d_internal.h"
 
@@ -1955,6 +1957,32 @@ hipError_t launch_combine_dot(Plan &p, const double *wts, double *acc)
     hipLaunchKernelGGL(k_combine_dot, dim3(nblk(p.Nx, 256)), dim3(256), 0, p.stream, p.d_uh, p.d_ul, p.d_tgt_rank, wts, acc,
                        p.Nx, p.d_step, p.lookahead);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed workspace for callers that cannot allocate (wfp2d_evaluate_noalloc).
+// In host code the array's name is only a stand-in: kernels get the address
+// returned by hipGetSymbolAddress, taken once per device with that device
+// current (each device holds its own copy of the array).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void **out)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = ptr;
+    *out = ptr;
+    return hipSuccess;
 }
 
 }  // namespace wfp2d
