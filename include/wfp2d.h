@@ -43,7 +43,8 @@ typedef enum {
     WFP2D_ERR_INFEASIBLE = -3,  /* parameters violate eq. dt, SOE validity, or device memory */
     WFP2D_ERR_NOMEM = -4,       /* device or host allocation failed */
     WFP2D_ERR_DEVICE = -5,      /* a HIP runtime call failed */
-    WFP2D_ERR_STATE = -6        /* call out of order (e.g. on a destroyed plan) */
+    WFP2D_ERR_STATE = -6,       /* call out of order (e.g. on a destroyed plan) */
+    WFP2D_ERR_NONFINITE = -7    /* a NaN or Inf sample was ingested while opts.check_finite was set */
 } wfp2d_status;
 
 enum { WFP2D_PREC_FP64 = 0, WFP2D_PREC_MIXED = 1 };
@@ -83,6 +84,20 @@ typedef struct {
      * dropped tail is at most 1e-3 tol of the largest coefficient (info.cheb_degree).
      * info.local_path reports the path taken. */
     int32_t local_pairs;
+    /* 0 (default): sigma and u of wfp2d_step / wfp2d_evaluate / wfp2d_evaluate_noalloc
+     * are device pointers, used in stream order.  1: they are host pointers; step
+     * copies sigma (through a pinned staging buffer) before it returns, and evaluate
+     * returns once u is written (it synchronises the plan's stream).  A plan with
+     * host pointers cannot be captured in a graph or a batch, and its
+     * wfp2d_evaluate_dot still takes device pointers. */
+    int32_t host_pointers;
+    /* 1: the ingest kernel tests every sample; a NaN or Inf is taken as 0 (so the
+     * plan's state stays finite) and raises a device-side flag.  The flag is
+     * reported, and cleared, by the next wfp2d_evaluate that sees it (copied back
+     * after each evaluation, so it may show one evaluation late) or by
+     * wfp2d_query (which synchronises the stream first), as WFP2D_ERR_NONFINITE.
+     * 0 (default): samples are not tested. */
+    int32_t check_finite;
 } wfp2d_opts;
 
 typedef struct {
@@ -155,7 +170,9 @@ wfp2d_status wfp2d_step(wfp2d_plan plan, const double *sigma);
  * [Nx] float64 in the order of tgt_xy.  u = u_h + u_l: the type-2 NUFFT of
  * the Fourier coefficients (eqs. uhtraptrunc, ufhApprox) plus the local part
  * (eq. ul_GL with the interpolation of eq. sigInterp).  For m <= 0 it writes
- * zeros (zero initial data, eq. wave2d).  Errors: ERR_ARG, ERR_STATE, ERR_DEVICE.
+ * zeros (zero initial data, eq. wave2d).  Errors: ERR_ARG, ERR_STATE, ERR_DEVICE;
+ * ERR_NONFINITE (u is still written) when opts.check_finite is set and a
+ * non-finite sample has been ingested since the flag was last reported.
  */
 wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u);
 
@@ -181,7 +198,9 @@ wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u);
  */
 wfp2d_status wfp2d_evaluate_noalloc(wfp2d_plan plan, double *u);
 
-/* Derived parameters and sizes of a plan.  Errors: ERR_ARG. */
+/* Derived parameters and sizes of a plan.  Errors: ERR_ARG; ERR_NONFINITE (with
+ * *info filled) when opts.check_finite is set and a non-finite sample has been
+ * ingested since the flag was last reported (the stream is synchronised first). */
 wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info);
 
 /* Release every resource of the plan (waits for its stream).  NULL is a no-op. */

@@ -25,7 +25,8 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "wfp2d.h")
 
 PREC_FP64, PREC_MIXED = 0, 1
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_DOMAIN", -3: "ERR_INFEASIBLE", -4: "ERR_NOMEM",
-          -5: "ERR_DEVICE", -6: "ERR_STATE"}
+          -5: "ERR_DEVICE", -6: "ERR_STATE", -7: "ERR_NONFINITE"}
+ERR_NONFINITE = -7
 
 
 class Wfp2dError(RuntimeError):
@@ -39,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("Delta", ctypes.c_double), ("a", ctypes.c_double), ("Kf", ctypes.c_double),
                 ("b_Delta", ctypes.c_double), ("nufft_tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("spread_tile", ctypes.c_int32),
-                ("local_pairs", ctypes.c_int32)]
+                ("local_pairs", ctypes.c_int32), ("host_pointers", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -156,13 +157,15 @@ class Wfp2d:
     def __init__(self, src_xy, tgt_xy, dt: float, W: int, tol: float = 1e-7, *, precision: str = "mixed",
                  interp_order: int = 20, lookahead: int = -1, Delta: float = 1.0, a: float = 0.0, Kf: float = 80.0,
                  b_Delta: float = 30.0, nufft_tol: float = 0.0, max_steps: int = 0, device: int = 0, stream=None,
-                 spread_tile: int = 0, local_pairs: bool = True):
+                 spread_tile: int = 0, local_pairs: bool = True, host_pointers: bool = False,
+                 check_finite: bool = False):
         import torch
         self._torch = torch
         self.lib = load_library()
         self._graph_keep = None
         if isinstance(src_xy, _Handle):              # adopt a plan made by the library (adjoint)
             self.h, self.device, self.stream = src_xy.h, src_xy.device, src_xy.stream
+            self.host_pointers = False
             inf = self.info()
             self.M, self.Nx, self._keep = inf["M"], inf["Nx"], []
             return
@@ -175,6 +178,8 @@ class Wfp2d:
         o.Delta, o.a, o.Kf, o.b_Delta, o.nufft_tol = float(Delta), float(a), float(Kf), float(b_Delta), float(nufft_tol)
         o.max_steps, o.device, o.spread_tile = int(max_steps), int(device), int(spread_tile)
         o.local_pairs = 0 if local_pairs else -1
+        o.host_pointers, o.check_finite = int(bool(host_pointers)), int(bool(check_finite))
+        self.host_pointers = bool(host_pointers)
         self.device = torch.device("cuda", int(device))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -202,6 +207,12 @@ class Wfp2d:
     # -- the hot path --
     def step(self, sigma):
         t = self._torch
+        if self.host_pointers:
+            a = np.ascontiguousarray(sigma, np.float64)
+            if a.size != self.M:
+                raise ValueError("sigma must hold M float64 values")
+            self._check(self.lib.wfp2d_step(self.h, a.ctypes.data_as(ctypes.c_void_p)))
+            return
         if not (isinstance(sigma, t.Tensor) and sigma.is_cuda and sigma.dtype == t.float64 and sigma.numel() == self.M):
             raise ValueError("sigma must be a float64 CUDA tensor with M elements")
         sigma = sigma.contiguous()
@@ -210,6 +221,13 @@ class Wfp2d:
 
     def evaluate(self, out=None):
         t = self._torch
+        if self.host_pointers:
+            out = np.empty(self.Nx, np.float64) if out is None else out
+            if not (isinstance(out, np.ndarray) and out.dtype == np.float64 and out.size == self.Nx
+                    and out.flags["C_CONTIGUOUS"]):
+                raise ValueError("out must be a contiguous float64 numpy array with Nx elements")
+            self._check(self.lib.wfp2d_evaluate(self.h, out.ctypes.data_as(ctypes.c_void_p)))
+            return out
         if out is None:
             out = t.empty(self.Nx, dtype=t.float64, device=self.device)
         if not (out.is_cuda and out.dtype == t.float64 and out.numel() == self.Nx and out.is_contiguous()):

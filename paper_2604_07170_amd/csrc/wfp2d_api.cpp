@@ -65,6 +65,10 @@ Plan::~Plan()
     if (stream) (void)hipStreamSynchronize(stream);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (ev_sig_copied) (void)hipEventDestroy(ev_sig_copied);
+    if (h_sig_stage) (void)hipHostFree(h_sig_stage);
+    if (h_u_stage) (void)hipHostFree(h_u_stage);
+    if (h_nonfinite) (void)hipHostFree(h_nonfinite);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void *ptr : allocs) (void)hipFree(ptr);
@@ -643,6 +647,21 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         }
         p.n_local_pairs = cnt;
     }
+    if (p.opts.host_pointers) {
+        p.d_sig_in = p.alloc<double>(M);
+        p.d_u_out = p.alloc<double>(Nx);
+        hip_check(hipHostMalloc((void **)&p.h_sig_stage, (size_t)M * sizeof(double), hipHostMallocDefault),
+                  "hipHostMalloc (sample staging)");
+        hip_check(hipHostMalloc((void **)&p.h_u_stage, (size_t)Nx * sizeof(double), hipHostMallocDefault),
+                  "hipHostMalloc (field staging)");
+        hip_check(hipEventCreateWithFlags(&p.ev_sig_copied, hipEventDisableTiming), "hipEventCreate");
+    }
+    if (p.opts.check_finite) {
+        p.d_nonfinite = p.alloc<unsigned long long>(1);
+        hip_check(hipHostMalloc((void **)&p.h_nonfinite, sizeof(unsigned long long), hipHostMallocDefault),
+                  "hipHostMalloc (non-finite count)");
+        *p.h_nonfinite = 0;
+    }
     p.state_bufs = {{p.d_step, sizeof(int64_t)},
                     {p.d_sig, (size_t)g.sig_depth * M * sizeof(double)},
                     {p.d_ring_cur, (size_t)p.W * p.n_modes * 2 * sr},
@@ -683,19 +702,58 @@ static void enqueue_evaluate(Plan &p, double *u, const double *dot_w = nullptr, 
         return e != hipSuccess ? e : launch_local(p);
     });
     timed(p, 11, "combine", [&] { return dot_acc ? launch_combine_dot(p, dot_w, dot_acc) : launch_combine(p, u); });
+    if (p.d_nonfinite)
+        hip_check(hipMemcpyAsync(p.h_nonfinite, p.d_nonfinite, sizeof(unsigned long long), hipMemcpyDeviceToHost, p.stream),
+                  "non-finite count copy");
+}
+
+// true (once per new count) when the ingest kernel has counted non-finite samples
+// that were not reported yet; reads the count copied back by the last finished evaluation
+static bool nonfinite_news(Plan &p)
+{
+    if (!p.h_nonfinite) return false;
+    const unsigned long long c = *(volatile unsigned long long *)p.h_nonfinite;
+    if (c == p.nonfinite_reported) return false;
+    p.nonfinite_reported = c;
+    return true;
+}
+
+// sample vector for the kernels: the caller's device pointer, or (host-pointer plans) a
+// device copy made through the pinned staging buffer; the caller's buffer is free on return
+static const double *stage_sigma(Plan &p, const double *sigma)
+{
+    if (!p.opts.host_pointers) return sigma;
+    hip_check(hipEventSynchronize(p.ev_sig_copied), "hipEventSynchronize");   // the previous copy has left the staging
+    std::memcpy(p.h_sig_stage, sigma, (size_t)p.M * sizeof(double));
+    hip_check(hipMemcpyAsync(p.d_sig_in, p.h_sig_stage, (size_t)p.M * sizeof(double), hipMemcpyHostToDevice, p.stream),
+              "sample copy");
+    hip_check(hipEventRecord(p.ev_sig_copied, p.stream), "hipEventRecord");
+    return p.d_sig_in;
+}
+
+// evaluation into the caller's u (device), or into the device staging then back to the caller's
+// host buffer (host-pointer plans; synchronises the stream)
+template <class F>
+static wfp2d_status evaluate_into(Plan &p, double *u, F &&enqueue)
+{
+    if (!p.opts.host_pointers) {
+        enqueue(u);
+        return nonfinite_news(p) ? WFP2D_ERR_NONFINITE : WFP2D_OK;
+    }
+    enqueue(p.d_u_out);
+    hip_check(hipMemcpyAsync(p.h_u_stage, p.d_u_out, (size_t)p.Nx * sizeof(double), hipMemcpyDeviceToHost, p.stream),
+              "field copy");
+    hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+    std::memcpy(u, p.h_u_stage, (size_t)p.Nx * sizeof(double));
+    return nonfinite_news(p) ? WFP2D_ERR_NONFINITE : WFP2D_OK;
 }
 
 static void do_step(Plan &p, const double *sigma)
 {
     hip_check(hipSetDevice(p.device), "hipSetDevice");
+    const double *s = stage_sigma(p, sigma);
     p.steps += 1;
-    enqueue_step(p, sigma);
-}
-
-static void do_evaluate(Plan &p, double *u)
-{
-    hip_check(hipSetDevice(p.device), "hipSetDevice");
-    enqueue_evaluate(p, u);
+    enqueue_step(p, s);
 }
 
 // capture `body` (which enqueues on `st`) into an executable graph
@@ -781,6 +839,8 @@ wfp2d_status wfp2d_default_opts(wfp2d_opts *o)
     o->stream = nullptr;
     o->spread_tile = 0;
     o->local_pairs = 0;
+    o->host_pointers = 0;
+    o->check_finite = 0;
     return WFP2D_OK;
 }
 
@@ -802,6 +862,8 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
         if (o.interp_order < 2 || o.interp_order > 32) fail(WFP2D_ERR_ARG, "interp_order must be in [2, 32]");
         if (o.spread_tile < 0 || o.spread_tile > 5) fail(WFP2D_ERR_ARG, "spread_tile must be in [0, 5]");
         if (o.local_pairs != 0 && o.local_pairs != -1) fail(WFP2D_ERR_ARG, "local_pairs must be 0 (auto) or -1 (never)");
+        if ((o.host_pointers != 0 && o.host_pointers != 1) || (o.check_finite != 0 && o.check_finite != 1))
+            fail(WFP2D_ERR_ARG, "host_pointers and check_finite must be 0 or 1");
         if (!(o.nufft_tol == 0.0 || (o.nufft_tol >= 1e-15 && o.nufft_tol < 1e-2)))
             fail(WFP2D_ERR_ARG, "nufft_tol must be 0 or in [1e-15, 1e-2) (kernel widths up to 16)");
         if (!(o.Delta > 0.0) || !(o.Kf > 0.0) || !(o.b_Delta > 0.0) || o.a < 0.0) fail(WFP2D_ERR_ARG, "bad Delta, Kf, b_Delta or a");
@@ -867,16 +929,21 @@ wfp2d_status wfp2d_step(wfp2d_plan plan, const double *sigma)
 wfp2d_status wfp2d_evaluate(wfp2d_plan plan, double *u)
 {
     if (!plan) return WFP2D_ERR_STATE;
+    wfp2d_status st = WFP2D_OK;
     WFP2D_GUARD(plan, {
         if (!u) fail(WFP2D_ERR_ARG, "NULL u");
-        do_evaluate(plan->p, u);
+        Plan &p = plan->p;
+        hip_check(hipSetDevice(p.device), "hipSetDevice");
+        st = evaluate_into(p, u, [&](double *dst) { enqueue_evaluate(p, dst); });
+        if (st == WFP2D_ERR_NONFINITE) p.err = "non-finite samples were ingested (taken as 0)";
     });
-    return WFP2D_OK;
+    return st;
 }
 
 wfp2d_status wfp2d_evaluate_noalloc(wfp2d_plan plan, double *u)
 {
     if (!plan) return WFP2D_ERR_STATE;
+    wfp2d_status st = WFP2D_OK;
     WFP2D_GUARD(plan, {
         Plan &p = plan->p;
         if (!u) fail(WFP2D_ERR_ARG, "NULL u");
@@ -892,6 +959,7 @@ wfp2d_status wfp2d_evaluate_noalloc(wfp2d_plan plan, double *u)
             fail(WFP2D_ERR_ARG, "evaluation workspace of " + std::to_string(need) + " bytes exceeds the fixed " +
                                     std::to_string(kScratchBytes) + "-byte workspace (use wfp2d_evaluate)");
         hip_check(hipSetDevice(p.device), "hipSetDevice");
+        if (p.opts.host_pointers && !p.d_u_out) fail(WFP2D_ERR_STATE, "no field staging");
         char *base = (char *)p.scratch;
         void *own[5] = {p.d_T2, p.d_T2t, p.d_cgrid, p.d_uh, p.d_ul};
         p.d_T2 = base;
@@ -900,14 +968,16 @@ wfp2d_status wfp2d_evaluate_noalloc(wfp2d_plan plan, double *u)
         p.d_uh = (double *)(base + 2 * t2 + cg);
         p.d_ul = (double *)(base + 2 * t2 + cg + uv);
         try {
-            enqueue_evaluate(p, u);   // each buffer is written in full before it is read (u_l by a fill kernel)
+            // each buffer is written in full before it is read (u_l by a fill kernel)
+            st = evaluate_into(p, u, [&](double *dst) { enqueue_evaluate(p, dst); });
         } catch (...) {
             p.d_T2 = own[0], p.d_T2t = own[1], p.d_cgrid = own[2], p.d_uh = (double *)own[3], p.d_ul = (double *)own[4];
             throw;
         }
         p.d_T2 = own[0], p.d_T2t = own[1], p.d_cgrid = own[2], p.d_uh = (double *)own[3], p.d_ul = (double *)own[4];
+        if (st == WFP2D_ERR_NONFINITE) p.err = "non-finite samples were ingested (taken as 0)";
     });
-    return WFP2D_OK;
+    return st;
 }
 
 wfp2d_status wfp2d_evaluate_dot(wfp2d_plan plan, const double *weights, double *acc)
@@ -918,6 +988,10 @@ wfp2d_status wfp2d_evaluate_dot(wfp2d_plan plan, const double *weights, double *
         Plan &p = plan->p;
         hip_check(hipSetDevice(p.device), "hipSetDevice");
         enqueue_evaluate(p, nullptr, weights, acc);
+        if (nonfinite_news(p)) {
+            p.err = "non-finite samples were ingested (taken as 0)";
+            return WFP2D_ERR_NONFINITE;
+        }
     });
     return WFP2D_OK;
 }
@@ -930,6 +1004,7 @@ wfp2d_status wfp2d_adjoint_init(wfp2d_plan *out, wfp2d_plan forward)
     const Plan &f = forward->p;
     wfp2d_opts o = f.opts;
     o.spread_tile = 0;
+    o.host_pointers = 0;   // the transposed plan is driven with device buffers
     return wfp2d_init(out, f.Nx, f.h_tgt_xy.data(), f.M, f.h_src_xy.data(), f.dt, f.W, f.tol, &o);
 }
 
@@ -1035,7 +1110,17 @@ wfp2d_status wfp2d_load_state(wfp2d_plan plan, const void *src, int64_t bytes)
 wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
 {
     if (!plan || !info) return WFP2D_ERR_ARG;
-    const Plan &p = plan->p;
+    Plan &p = plan->p;
+    bool nonfinite = false;
+    if (p.d_nonfinite) {
+        WFP2D_GUARD(plan, {
+            hip_check(hipSetDevice(p.device), "hipSetDevice");
+            hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+            hip_check(hipMemcpy(p.h_nonfinite, p.d_nonfinite, sizeof(unsigned long long), hipMemcpyDeviceToHost),
+                      "non-finite count copy");
+            nonfinite = nonfinite_news(p);
+        });
+    }
     std::memset(info, 0, sizeof *info);
     info->dt = p.dt;
     info->delta = p.delta;
@@ -1077,6 +1162,10 @@ wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
     info->local_path = p.local_pairs ? 2 : p.local_fast ? 1 : 0;
     info->local_pair_bytes = p.pair_bytes;
     info->n_regular_subpanels = p.n_reg;
+    if (nonfinite) {
+        p.err = "non-finite samples were ingested (taken as 0)";
+        return WFP2D_ERR_NONFINITE;
+    }
     return WFP2D_OK;
 }
 
@@ -1150,6 +1239,7 @@ wfp2d_status wfp2d_graph_capture(wfp2d_plan plan, const double *sigma, double *u
         Plan &p = plan->p;
         if (!sigma || !u) fail(WFP2D_ERR_ARG, "NULL pointer");
         if (p.timing) fail(WFP2D_ERR_STATE, "stage timing is enabled");
+        if (p.opts.host_pointers) fail(WFP2D_ERR_STATE, "a plan with host pointers cannot be captured");
         if (!p.stream) fail(WFP2D_ERR_STATE, "graph capture needs a non-default stream");
         hip_check(hipSetDevice(p.device), "hipSetDevice");
         capture_graph(p.stream, p.graph, p.graph_exec, [&] {
@@ -1185,6 +1275,7 @@ wfp2d_status wfp2d_batch_create(wfp2d_batch *out, int32_t n, const wfp2d_plan *p
             if (!plans[i] || !sigma[i] || !u[i]) fail(WFP2D_ERR_ARG, "NULL plan or pointer in batch");
             if (plans[i]->p.device != dev) fail(WFP2D_ERR_ARG, "batch plans must share a device");
             if (plans[i]->p.timing) fail(WFP2D_ERR_STATE, "stage timing is enabled on a batch plan");
+            if (plans[i]->p.opts.host_pointers) fail(WFP2D_ERR_STATE, "a batch plan has host pointers");
         }
         if (!stream) fail(WFP2D_ERR_ARG, "a batch needs a non-default stream");
         b = new wfp2d_batch_s();

@@ -66,7 +66,7 @@ struct Plan;
 
 // ---- launchers (kernels file) ----
 hipError_t launch_step_begin(Plan &p);
-hipError_t launch_ingest(Plan &p, const double *sigma_in);
+hipError_t launch_ingest(Plan &p, const double *sigma_in);   // tests samples when p.d_nonfinite is set
 hipError_t launch_spread(Plan &p);
 hipError_t kernel_setup(Plan &p);
 hipError_t fft_setup(Plan &p);
@@ -187,6 +187,15 @@ struct Plan {
     double *d_pair_dw = nullptr;      // eta_d(r) of each pair with r < dt/2, [n_dy_pairs][nlev]
     int32_t n_cu = 256;               // compute units of the device (persistent grids)
     void *scratch = nullptr;          // this device's fixed workspace (see scratch_address)
+    // host-pointer mode: device and pinned host staging of one sample vector and one field
+    double *d_sig_in = nullptr, *d_u_out = nullptr;
+    double *h_sig_stage = nullptr, *h_u_stage = nullptr;   // hipHostMalloc
+    hipEvent_t ev_sig_copied = nullptr;                     // the last sample copy has left h_sig_stage
+    // non-finite check: device count of non-finite samples (ingest kernel), copied to pinned
+    // host memory after each evaluation; counts up to `nonfinite_reported` have been reported
+    unsigned long long *d_nonfinite = nullptr;
+    unsigned long long *h_nonfinite = nullptr;              // hipHostMalloc, one word
+    unsigned long long nonfinite_reported = 0;
     uint64_t *d_pair_pw = nullptr;    // regular pairs, one packed word each
     uint32_t *d_pair_dent = nullptr;
 

@@ -47,12 +47,19 @@ __device__ __forceinline__ int64_t pmod(int64_t a, int64_t b) { return ((a % b) 
 
 __global__ void k_step_begin(int64_t *step) { step[0] += 1; }
 
-// sigma ingest: ring slot of step n <- caller's samples gathered into sorted order
+// sigma ingest: ring slot of step n <- caller's samples gathered into sorted order.
+// With a counter, a non-finite sample is stored as 0 and counted.
 __global__ void k_ingest(const double *__restrict__ in, const int32_t *__restrict__ perm, double *__restrict__ sig, int64_t M,
-                         const int64_t *__restrict__ step, int64_t depth)
+                         const int64_t *__restrict__ step, int64_t depth, unsigned long long *__restrict__ nonfinite)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < M) sig[pmod(step[0], depth) * M + j] = in[perm[j]];
+    if (j >= M) return;
+    double v = in[perm[j]];
+    if (nonfinite && !isfinite(v)) {
+        v = 0.0;
+        atomicAdd(nonfinite, 1ull);
+    }
+    sig[pmod(step[0], depth) * M + j] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1633,7 +1640,7 @@ hipError_t launch_step_begin(Plan &p)
 hipError_t launch_ingest(Plan &p, const double *sigma_in)
 {
     hipLaunchKernelGGL(k_ingest, dim3(nblk(p.M, 256)), dim3(256), 0, p.stream, sigma_in, p.d_src_perm, p.d_sig, p.M, p.d_step,
-                       p.g.sig_depth);
+                       p.g.sig_depth, p.d_nonfinite);
     return hipGetLastError();
 }
 

@@ -103,3 +103,18 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_boundary_options_default_off_and_are_validated():
+    lib = pa.load_library()
+    o = pa.Opts()
+    lib.wfp2d_default_opts(ctypes.byref(o))
+    assert o.host_pointers == 0 and o.check_finite == 0
+    plan = ctypes.c_void_p()
+    xy = (ctypes.c_double * 2)(0.0, 0.0)
+    o.host_pointers = 2
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.05, 24, 1e-7, ctypes.byref(o)) == -1
+    o.host_pointers, o.check_finite = 0, 5
+    assert lib.wfp2d_init(ctypes.byref(plan), 1, xy, 1, xy, 0.05, 24, 1e-7, ctypes.byref(o)) == -1
+    assert b"check_finite" in lib.wfp2d_last_error(None)
+    assert pa.STATUS[-7] == "ERR_NONFINITE"
