@@ -19,6 +19,7 @@ def _in_b(x):
     (4, 1_000_000, 1_000_000, 8 / 7150, 16, 6000, FAMILY_E),
     (5, 100_000, 810_000, 8 / 7150, 16, 7150, FAMILY_E),
     (6, 1_000_000, 810_000, 8 / 7150, 16, 7150, FAMILY_E),
+    (7, 1_000_000, 810_000, 8 / 7150, 16, 7150, FAMILY_E),
 ])
 def test_configuration_recipe(idx, M, Nx, dt, W, nt, fam):
     w = config(idx)
@@ -31,12 +32,17 @@ def test_configuration_recipe(idx, M, Nx, dt, W, nt, fam):
     if fam == FAMILY_E:
         L = w.meta["L"]
         assert np.all((w.omega >= 0) & (w.omega <= math.pi * L))
-    if idx in (2, 4):
+    if idx in (2, 4, 7):
         T = w.dt * w.nt
         assert np.all((w.t0 >= 1.5 * T / 8) & (w.t0 <= 7.0 * T / 8))
+    if idx == 7:
+        # Sec. 7.2 as run in the paper: T = 8, t0 in [1.5, 7], omega = 300 pi z^(1/3)
+        assert w.dt * w.nt == pytest.approx(8.0)
+        assert np.median(w.omega) == pytest.approx(300 * math.pi * 0.5 ** (1 / 3), rel=0.01)
     if idx in (5, 6):
         frac = np.arange(M) / M
         assert np.allclose(w.t0, 1.5 + 5.5 * frac)
+    if idx in (5, 6, 7):
         # the 900 x 900 mesh: cell centres of a 900 x 900 partition of B
         xs = np.unique(w.tgt[:, 0])
         assert xs.size == 900 and np.allclose(np.diff(xs), 2 / 900)

@@ -260,6 +260,13 @@ def config(idx: int, displaced_targets: bool = False) -> Workload:
         src = uniform_square(rng, 1_000_000)
         w = family_e_workload("cfg4_M1e6_300wl_E", rng, src, L=300.0, nt=6000, dt=8.0 / 7150.0,
                               T_ref=8.0 / 7150.0 * 6000)
+    elif idx == 7:
+        # the random space-filling example of Sec. 7.2 as the paper runs it: the 10^6 random
+        # sources of the 300-wavelength workload's recipe with T = 8 (t0 in [1.5, 7]), targets
+        # on the separate 900 x 900 mesh (no target on a source)
+        src = uniform_square(rng, 1_000_000)
+        w = family_e_workload("cfg7_random_M1e6_grid900", rng, src, L=300.0, nt=7150, dt=8.0 / 7150.0, T_ref=8.0,
+                              tgt=grid_targets(900))
     elif idx in (5, 6):
         # the curve examples of Sec. 5: the Sec. 5.2 step, window and final time T = 8, a
         # 900 x 900 target mesh (no target on a source), t0 rising from 1.5 to 7 along the
