@@ -109,11 +109,15 @@ def n_max(info: dict) -> int:
 
 
 def local_impl_flops(info: dict) -> int:
-    """FP64 flops of the local kernel as executed: per source, the Chebyshev profile on every
-    regular sub-panel (each coefficient a dot product over the sigma levels); per pair, one
-    Clenshaw evaluation (2 flops per term) plus distance and sub-panel coordinate (~12 flops)."""
-    return (2 * info["M"] * info["n_regular_subpanels"] * info["cheb_degree"] * info["n_levels"]
-            + info["n_local_pairs"] * (2 * info["cheb_degree"] + 12))
+    """FP64 flops of the local kernel as executed: per source, the polynomial profile on every
+    regular sub-panel (each coefficient a dot product over the sigma levels); with stored pair
+    lists, per list entry (pairs and run padding) one Horner evaluation (2 flops per term) plus
+    the decoded coordinate (2 flops); with the per-step pair search, per pair one Clenshaw
+    evaluation plus distance and sub-panel coordinate (~12 flops)."""
+    prof = 2 * info["M"] * info["n_regular_subpanels"] * info["cheb_degree"] * info["n_levels"]
+    if info.get("local_pair_words", 0) > 0:
+        return prof + info["local_pair_words"] * (2 * info["cheb_degree"] + 2)
+    return prof + info["n_local_pairs"] * (2 * info["cheb_degree"] + 12)
 
 
 def stage_kernel(stage: str, info: dict):
@@ -378,7 +382,7 @@ def run_form(args, w, precision: str, dev, log, golden: dict) -> dict:
     n_first = first + L                                   # first timed ingested step
     Wu = min(Wu, n_first - 1)
     log(f"[bench] {w.name} {precision}: plan ready in {init_s:.1f}s  modes={info['n_modes']} nf={info['nf']} "
-        f"band={info['band']} pairs={info['n_local_pairs']} lookahead={L} HBM={info['bytes_device'] / 2**30:.1f}GiB; "
+        f"band={info['band']} pairs={info['n_local_pairs']} pair_words={info['local_pair_words']} lookahead={L} HBM={info['bytes_device'] / 2**30:.1f}GiB; "
         f"timed steps report u(t_{first}..t_{last})")
     params = w.torch_params(dev)
     tuning = None

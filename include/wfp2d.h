@@ -127,6 +127,9 @@ typedef struct {
     int32_t spread_tile;         /* current spreading tile shape code */
     int32_t local_path;          /* local-part kernel: 0 generic, 1 per-step pair search, 2 stored pair lists */
     int64_t local_pair_bytes;    /* device bytes of the stored pair lists (0 if none) */
+    int64_t local_pair_words;    /* entries of the stored regular pair lists: pairs with r >= dt/2 and
+                                    the padding that completes each (source, sub-panel) group to whole
+                                    runs of 8 (0 if none) */
 } wfp2d_info;
 
 /* Fill *opts with the defaults listed above.  Never fails for a valid pointer. */

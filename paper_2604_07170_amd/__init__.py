@@ -54,7 +54,7 @@ class Info(ctypes.Structure):
                                                  "steps_ingested", "step_reported")]
                 + [("precision", ctypes.c_int32), ("n_regular_subpanels", ctypes.c_int32),
                    ("spread_tile", ctypes.c_int32), ("local_path", ctypes.c_int32),
-                   ("local_pair_bytes", ctypes.c_int64)])
+                   ("local_pair_bytes", ctypes.c_int64), ("local_pair_words", ctypes.c_int64)])
 
 
 _lib = None

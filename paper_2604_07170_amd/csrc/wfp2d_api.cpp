@@ -233,19 +233,28 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
     int64_t *d_cnt = p.alloc<int64_t>(nslot), *d_dcnt = p.alloc<int64_t>(nslot);
     hip_check(launch_pairs_build(p, false, d_cnt, d_dcnt), "pair count");
     hip_check(hipStreamSynchronize(p.stream), "pair count");
-    std::vector<int64_t> cnt(nslot), dcnt(nslot), off(nslot + 1, 0), doff(nslot + 1, 0);
+    std::vector<int64_t> cnt(nslot), dcnt(nslot), off(nslot + 1, 0), doff(nslot + 1, 0), seg_end(nslot / kFastSrc);
     hip_check(hipMemcpy(cnt.data(), d_cnt, nslot * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy D2H");
     hip_check(hipMemcpy(dcnt.data(), d_dcnt, nslot * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy D2H");
     p.release(d_cnt);
     p.release(d_dcnt);
+    // regular pairs: each segment's slots back to back, each (slot, panel) group in whole runs
+    int64_t npair = 0, nreal = 0;
     for (int64_t s = 0; s < nslot; ++s) {
-        off[s + 1] = off[s] + cnt[s];
+        off[s] = npair;
+        npair += cnt[s] & 0xFFFFFFFF;                 // words: pairs and the padding of each panel's run
+        nreal += cnt[s] >> 32;
+        if ((s + 1) % kFastSrc == 0) {
+            npair = (npair + kPairBlockPad - 1) / kPairBlockPad * kPairBlockPad;
+            seg_end[s / kFastSrc] = npair;
+        }
         doff[s + 1] = doff[s] + dcnt[s];
     }
-    const int64_t npair = off.back(), ndy = doff.back();
+    off[nslot] = npair;
+    const int64_t ndy = doff.back();
     const int64_t bytes = npair * (int64_t)sizeof(uint64_t) +
-                          ndy * (int64_t)(sizeof(uint32_t) + p.g.nlev * sizeof(double)) +
-                          2 * (nslot + 1 + nslot / kFastSrc + 1) * (int64_t)sizeof(int64_t);
+                          ndy * (int64_t)(3 * sizeof(uint32_t) + p.g.nlev * sizeof(double)) +
+                          2 * (nslot + 1) * (int64_t)sizeof(int64_t);
     size_t free_b = 0, total_b = 0;
     hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     if ((double)bytes > 0.5 * (double)free_b) {
@@ -259,27 +268,51 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
     p.d_pair_doff = p.alloc<int64_t>(nslot + 1);
     upload(p.d_pair_off, off);
     upload(p.d_pair_doff, doff);
-    {
-        // the same offsets per segment (every kFastSrc-th), read by the per-step kernel
-        const int64_t nseg = nslot / kFastSrc;
-        std::vector<int64_t> so(nseg + 1), sdo(nseg + 1);
-        for (int64_t s = 0; s <= nseg; ++s) {
-            so[s] = off[s * kFastSrc];
-            sdo[s] = doff[s * kFastSrc];
-        }
-        p.d_seg_off = p.alloc<int64_t>(nseg + 1);
-        p.d_seg_doff = p.alloc<int64_t>(nseg + 1);
-        upload(p.d_seg_off, so);
-        upload(p.d_seg_doff, sdo);
-    }
+    p.pair_nword = npair;
     p.d_pair_pw = p.alloc<uint64_t>(npair);
     p.d_pair_dent = p.alloc<uint32_t>(ndy);
     p.d_pair_dw = p.alloc<double>(ndy * p.g.nlev);
+    p.d_pair_dtg = p.alloc<int32_t>(ndy);
+    p.d_pair_dsg = p.alloc<int32_t>(ndy);
+    p.pair_ndy = ndy;
     hip_check(launch_pairs_build(p, true, nullptr, nullptr), "pair fill");
     hip_check(hipStreamSynchronize(p.stream), "pair fill");
+    {
+        // items of the producer / consumer local kernel: workgroup g takes work units g, g + G, ...,
+        // each unit batch by batch, each batch chunk by chunk (one segment per item)
+        const int64_t G = std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, p.n_cu));
+        struct Desc {
+            int64_t p0, p1;
+            int32_t sb, ns, wk, b;
+        };
+        static_assert(sizeof(Desc) == 32, "item descriptor layout");
+        std::vector<Desc> items;
+        std::vector<int32_t> ioff(1, 0);
+        for (int64_t g = 0; g < G; ++g) {
+            for (int64_t wk = g; wk < p.pair_n_work; wk += G) {
+                const int32_t *rec = &wrec[(size_t)wk * kPairRec];
+                const int s0 = rec[0], s1 = rec[1], NT = rec[12];
+                const int nb = (NT + kPairTB - 1) / kPairTB, nch = (s1 - s0 + kFastSrc - 1) / kFastSrc;
+                for (int b = 0; b < nb; ++b)
+                    for (int c = 0; c < nch; ++c) {
+                        const int64_t seg = wseg[wk] + (int64_t)c * nb + b;
+                        const int sb = s0 + c * kFastSrc;
+                        items.push_back(Desc{off[seg * kFastSrc], seg_end[seg], sb, std::min(kFastSrc, s1 - sb),
+                                             (int32_t)wk, b});
+                    }
+            }
+            if ((int64_t)items.size() > INT32_MAX) return;
+            ioff.push_back((int32_t)items.size());
+        }
+        p.d_pc_desc = p.alloc<Desc>((int64_t)items.size());
+        upload((Desc *)p.d_pc_desc, items);
+        p.d_pc_ioff = p.alloc<int32_t>((int64_t)ioff.size());
+        upload(p.d_pc_ioff, ioff);
+        p.pc_grid = (int32_t)G;
+    }
     p.local_pairs = true;
     p.pair_bytes = bytes;
-    p.n_local_pairs = npair + ndy;
+    p.n_local_pairs = nreal + ndy;
 }
 
 static void build(Plan &p, const double *src_xy, const double *tgt_xy)
@@ -620,15 +653,30 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_panel_base, LT.panel_base);
     p.d_panel_l2n = p.alloc<int32_t>(p.W);
     upload(p.d_panel_l2n, LT.panel_l2n);
-    if (p.local_fast && p.W <= 64 && p.n_reg * kChebDeg <= kPairThreads / 64 * kPairRB * 16 && p.opts.local_pairs == 0)
+    // Mixed precision: the pair-list kernel evaluates only the leading terms of each regular
+    // panel's series when the dropped ones sum to at most 1e-3 tol, relative to the largest
+    // coefficient (the scale of the fit criterion of the tables).  Measured, the field then
+    // moves by about ten times that bound, two orders of magnitude below tol; FP64 plans use
+    // every stored term.
+    p.local_terms = p.precision == WFP2D_PREC_MIXED ? local_table_terms(LT, p.tol) : kChebDeg;
+    if (p.local_fast && p.W <= 64 && pc_producers(p.n_reg, p.local_terms) > 0 && p.opts.local_pairs == 0)
         build_pair_lists(p, cell_start, tcell_start);
-    if (p.local_pairs && p.precision == WFP2D_PREC_MIXED) {
-        // Mixed precision: evaluate only the leading terms of each regular panel's series when
-        // the dropped ones sum to at most 1e-3 tol, relative to the largest coefficient (the
-        // scale of the fit criterion of the tables).  Measured, the field then moves by about
-        // ten times that bound, two orders of magnitude below tol; FP64 plans use every
-        // stored term.
-        p.local_terms = local_table_terms(LT, p.tol);
+    if (!p.local_pairs) p.local_terms = kChebDeg;
+    if (p.local_pairs) {
+        // the pair kernel sums each regular panel's truncated series by Horner's rule: the
+        // same polynomials in the power basis, [n_reg][kChebDeg][nlev] (terms beyond
+        // local_terms zero), scaled by 1/(2 pi)
+        const int nl = LT.nlev, D = p.local_terms;
+        const double s2pi = 0.5 / M_PI;
+        std::vector<double> cpow((size_t)p.n_reg * kChebDeg * nl, 0.0), b(kChebDeg), a(kChebDeg);
+        for (int sp = 0; sp < p.n_reg; ++sp)
+            for (int d = 0; d < nl; ++d) {
+                for (int c = 0; c < kChebDeg; ++c) b[c] = LT.coef[((size_t)sp * nl + d) * kChebDeg + c];
+                cheb_to_power(b.data(), D, a.data());
+                for (int c = 0; c < D; ++c) cpow[((size_t)sp * kChebDeg + c) * nl + d] = s2pi * a[c];
+            }
+        p.d_cpow = p.alloc<double>((int64_t)cpow.size());
+        upload(p.d_cpow, cpow);
     }
     // local-pair count (reported; without pair lists the local kernel finds pairs through the cell lists)
     if (!p.local_pairs) {
@@ -1161,6 +1209,7 @@ wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
     info->spread_tile = p.spread_tile;
     info->local_path = p.local_pairs ? 2 : p.local_fast ? 1 : 0;
     info->local_pair_bytes = p.pair_bytes;
+    info->local_pair_words = p.local_pairs ? p.pair_nword : 0;
     info->n_regular_subpanels = p.n_reg;
     if (nonfinite) {
         p.err = "non-finite samples were ingested (taken as 0)";
@@ -1498,6 +1547,22 @@ wfp2d_status wfp2d_host_eval(int32_t what, const double *in, int64_t n_in, doubl
             out[1] = tail;
             out[2] = cmax;
             for (int64_t i = 0; i < k; ++i) local_table_eval(T, dt, W, in[5 + i], out + 3 + i * T.nlev, terms);
+            break;
+        }
+        case 10: {
+            if (n_in < 6) fail(WFP2D_ERR_ARG, "need dt, W, p, lookahead, tol, terms");
+            const double dt = in[0], tol = in[4];
+            const int W = (int)in[1], p = (int)in[2], terms = (int)in[5];
+            int look = (int)in[3];
+            if (look < 0) look = (p + 1) / 2 - 1;
+            if (!(dt > 0) || W < 2 || p < 2 || !(tol > 0 && tol < 1) || terms < 2 || terms > kChebDeg)
+                fail(WFP2D_ERR_ARG, "bad local parameters");
+            Blend phi(W * dt, std::log(1.0 / tol), 160);
+            LocalWeights LW(dt, W, p, -look, phi);
+            LocalTable T = build_local_table(LW, 40, 1e-11);
+            const int64_t k = n_in - 6;
+            need(k * T.nlev);
+            for (int64_t i = 0; i < k; ++i) local_table_eval_power(T, dt, W, in[6 + i], out + i * T.nlev, terms);
             break;
         }
         case 7: {

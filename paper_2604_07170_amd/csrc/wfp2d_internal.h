@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -29,10 +30,29 @@ constexpr int kFastRow = 512;      //   max coefficient rows (regular sub-panels
 constexpr int kPairTB = 1024;      // pair-list local kernel: targets per batch (LDS sums)
 constexpr int kPairRec = 16;       //   int32 per work-cell record
 constexpr int kPairUnit = 4;       //   adjacent cells of a row per work unit
-constexpr int kPairThreads = 1024; //   threads per workgroup: 16 waves, one workgroup per CU, or
-constexpr int kPairThreadsHalf = 512; //   8 waves, two per CU, when the rows fit 8 x kPairRB blocks
-constexpr int kPairRB = 2;         //   16-row blocks of the coefficient table per wave
 constexpr int kFastOwn = 4;        //   targets owned per thread
+constexpr int kPairBlockPad = 8;   // pair-list segments are whole runs of this many pairs
+constexpr int kPcMaxRows = 480;    // producer / consumer local kernel: profile rows per source
+constexpr int kPcLdsRows = 256;    //   rows of the variant with the power-basis table in LDS
+// producer waves of the producer / consumer local kernel and its 16-row MFMA blocks per producer
+// (rb: 2 up to 384 rows, with the A operands held in registers; else 3, read from cache at each
+// item), at least 4 of its 16 waves left to evaluate pairs; 0 when the profile rows do not fit it
+// (rb 4: up to kPcLdsRows rows of 35 levels, the table in LDS and 4 producers, 12 waves left for
+// the pairs)
+inline int pc_producers(int n_reg, int terms, int *rb = nullptr, int nlev = 0)
+{
+    const int rows = n_reg * terms, nblk = (rows + 15) / 16;
+    if (nlev == 35 && rows <= kPcLdsRows && terms % 2 == 0 && terms <= 16) {
+        if (rb) *rb = 4;
+        return 4;
+    }
+    const int r = nblk <= 24 ? 2 : 3, nprod = (nblk + r - 1) / r;
+    if (rb) *rb = r;
+    return (terms % 2 == 0 && rows <= kPcMaxRows && (r == 2 || terms == 20) && nprod <= 12) ? nprod : 0;
+}
+// dynamic LDS of the producer / consumer kernel: two profile buffers of up to kPcMaxRows rows
+constexpr size_t kPcDynLds = std::max((size_t)2 * 16 * (kPcMaxRows + 2) * 8,
+                                      (size_t)2 * 16 * (kPcLdsRows + 2) * 8 + (size_t)kPcLdsRows * 36 * 8);
 // fixed device workspace of wfp2d_evaluate_noalloc (one per device, held until the process ends)
 constexpr size_t kScratchBytes = size_t(64) << 20;
 
@@ -170,6 +190,7 @@ struct Plan {
     SubPanel *d_subs = nullptr;
     double *d_cheb = nullptr;         // [n_sub][nlev][kChebDeg], scaled by 1/(2 pi)
     double *d_creg = nullptr;         // regular sub-panels [n_reg][kChebDeg][nlev], scaled by 1/(2 pi)
+    double *d_cpow = nullptr;         //   the same, truncated to local_terms and in the power basis (pair kernel)
     int32_t n_reg = 0, local_sc = 1;  // regular sub-panels; sources per chunk in the local kernel
     bool local_fast = false;          // one sub-panel per time-step panel and a supported level count
     int32_t *d_panel_base = nullptr;  // regular panel k -> first sub-panel, and log2 count
@@ -183,7 +204,7 @@ struct Plan {
     int32_t *d_pair_wrec = nullptr;   // their records: s0, s1, rbeg[5], rcum[6], padding (16 int32)
     int64_t *d_pair_wseg = nullptr;   // first segment of each work cell, [n_work + 1]
     int64_t *d_pair_off = nullptr, *d_pair_doff = nullptr;   // [n_seg * kFastSrc + 1]
-    int64_t *d_seg_off = nullptr, *d_seg_doff = nullptr;     // first pair of each segment, [n_seg + 1]
+    int64_t pair_nword = 0;           // pair words, segments padded to whole 256-pair blocks
     double *d_pair_dw = nullptr;      // eta_d(r) of each pair with r < dt/2, [n_dy_pairs][nlev]
     int32_t n_cu = 256;               // compute units of the device (persistent grids)
     void *scratch = nullptr;          // this device's fixed workspace (see scratch_address)
@@ -198,6 +219,11 @@ struct Plan {
     unsigned long long nonfinite_reported = 0;
     uint64_t *d_pair_pw = nullptr;    // regular pairs, one packed word each
     uint32_t *d_pair_dent = nullptr;
+    int32_t *d_pair_dtg = nullptr, *d_pair_dsg = nullptr;   // pairs with r < dt/2: sorted target, source
+    int64_t pair_ndy = 0;
+    void *d_pc_desc = nullptr;        // producer / consumer kernel: item descriptors (32 bytes each)
+    int32_t *d_pc_ioff = nullptr;     //   first item of each workgroup
+    int32_t pc_grid = 0;              //   workgroups (one per CU); 0 = kernel not used
 
     std::string err;
 

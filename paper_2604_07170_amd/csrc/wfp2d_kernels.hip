@@ -756,6 +756,7 @@ struct LocalArgs {
     const int32_t *scell_start, *tcell_start;
     const SubPanel *subs;
     const double *cheb, *creg;
+    const double *cpow;   // regular panels' truncated series in the power basis (pair kernel)
     const int32_t *pbase, *pl2n;
     const double *sig;
     double *ul;
@@ -794,6 +795,46 @@ __device__ __forceinline__ void cheb_eval2n(const double *c0, double x0, const d
     }
     v0 = fma(x0, a1, c0[0] - a2);
     v1 = fma(x1, b1, c1[0] - b2);
+}
+
+// two power-basis polynomials of NT (even) coefficients summed by Horner's rule, interleaved;
+// coefficients read two at a time (16-byte aligned rows)
+template <int NT>
+__device__ __forceinline__ void horner2n(const double *c0, double x0, const double *c1, double x1, double &v0, double &v1)
+{
+    static_assert(NT % 2 == 0, "coefficient pairs");
+    const double2 *a = reinterpret_cast<const double2 *>(c0), *b = reinterpret_cast<const double2 *>(c1);
+    double2 ta = a[NT / 2 - 1], tb = b[NT / 2 - 1];
+    double y0 = fma(ta.y, x0, ta.x), y1 = fma(tb.y, x1, tb.x);
+#pragma unroll
+    for (int j = NT / 2 - 2; j >= 0; --j) {
+        ta = a[j];
+        tb = b[j];
+        y0 = fma(fma(y0, x0, ta.y), x0, ta.x);
+        y1 = fma(fma(y1, x1, tb.y), x1, tb.x);
+    }
+    v0 = y0;
+    v1 = y1;
+}
+
+// four power-basis polynomials of NT (even) coefficients (rows of 16-byte coefficient pairs)
+// summed by Horner's rule, interleaved
+template <int NT>
+__device__ __forceinline__ void horner4n(const double2 *const (&r)[4], const double (&x)[4], double (&y)[4])
+{
+    static_assert(NT % 2 == 0, "coefficient pairs");
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 t = r[i][NT / 2 - 1];
+        y[i] = fma(t.y, x[i], t.x);
+    }
+#pragma unroll
+    for (int j = NT / 2 - 2; j >= 0; --j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 t = r[i][j];
+            y[i] = fma(fma(y[i], x[i], t.y), x[i], t.x);
+        }
 }
 
 __device__ __forceinline__ void cheb_eval2(const double *c0, double x0, const double *c1, double x1, double &v0, double &v1)
@@ -1254,52 +1295,81 @@ __global__ __launch_bounds__(kFastRow) void k_local_fast(LocalArgs A, const int6
 // one 64-bit word (pair_pack:
 // target in the batch, source in the chunk, panel k, Chebyshev coordinate x);
 // for a pair with r < dt/2 (dyadic sub-panels) the word t | s << 16 and its
-// weights eta_d(r).  Within a segment the pairs are ordered by source, then by
-// target.
+// weights eta_d(r).  Within a segment the regular pairs are ordered by source,
+// then panel, then target (so the pairs of a 64-lane block mostly read one
+// profile row: LDS broadcasts).
 // k_local_pairs then does, per step and chunk: the profile coefficients
-// psi = C sigma with FP64 MFMA (as k_local_fast), then its waves take 128-pair
-// blocks of the segment in turn, two interleaved Clenshaw sums per lane, with
-// per-target sums in LDS; there is no candidate test, compaction or square
-// root per pair, and every wave gets the same number of pairs.
+// psi = C sigma with FP64 MFMA, C being each regular panel's truncated series
+// in the power basis, then its waves take 128-pair blocks of the segment in
+// turn, two interleaved Horner sums per lane, with per-target sums in LDS;
+// there is no candidate test, compaction or square root per pair, and every
+// wave gets the same number of pairs.
 // ---------------------------------------------------------------------------
 static_assert(kFastSrc <= 16 && kPairTB <= 1024, "pair words hold the target in 10 bits and the source in 4");
 
-// A regular pair in one 64-bit word: target in batch (bits 0-9), source in chunk
-// (10-13), panel (14-19), and the Chebyshev coordinate x in [-1, 1] as a 44-bit
-// fixed-point fraction (20-63; resolution 1.1e-13).
-constexpr double kPairXScale = 2.0 / 17592186044415.0;   // 2 / (2^44 - 1)
-__device__ __forceinline__ uint64_t pair_pack(int t, int s, int k, double x)
+// A regular pair in one 64-bit word: its target in the batch (bits 0-10; 1024 and above:
+// private sums of the padding entries), the LDS offset of its profile row in 16-byte units
+// (bits 11-22: s psiSrc + k D doubles for source s of the chunk and panel k), and its
+// Chebyshev coordinate x in [-1, 1] as the 41-bit fraction f = (x + 1) / 2 (bits 23-63;
+// resolution 9.1e-13), which under the exponent bits of 1.0 is the double 1 + f.
+// Within a slot the pairs of each panel are padded to whole runs of kRunPairs with padding
+// entries (target 1024 + e mod 128, the panel's profile row, x = 0), which add to private sums
+// past the targets': every run of an item's list shares one profile row.
+constexpr int kRunPairs = 8;
+constexpr int kPcFlushRounds = (kPairTB + 255) / 256;   // flush rounds of the local kernel's consumers (at least 4 waves)
+constexpr int kPairTBPad = kPairTB + 128;             // per-target sums plus the padding entries' sums
+__device__ __forceinline__ uint64_t pair_pack(int t, int row16, double x)
 {
-    const uint64_t q = (uint64_t)llrint((fmin(1.0, fmax(-1.0, x)) + 1.0) / kPairXScale);
-    return (uint64_t)t | ((uint64_t)s << 10) | ((uint64_t)k << 14) | (q << 20);
+    const double f = 0.5 * (fmin(1.0, fmax(-1.0, x)) + 1.0);
+    const uint64_t q = min((uint64_t)llrint(f * 2199023255552.0), (uint64_t)2199023255551ull);   // 2^41 f
+    return (uint64_t)t | ((uint64_t)row16 << 11) | (q << 23);
 }
-__device__ __forceinline__ int pair_t(uint64_t w) { return (int)(w & 1023u); }
-__device__ __forceinline__ int pair_s(uint64_t w) { return (int)((w >> 10) & 15u); }
-__device__ __forceinline__ int pair_k(uint64_t w) { return (int)((w >> 14) & 63u); }
-__device__ __forceinline__ double pair_x(uint64_t w) { return fma((double)(w >> 20), kPairXScale, -1.0); }
+__device__ __forceinline__ uint64_t pair_pad(int64_t e) { return (uint64_t)(1024 + (e & 127)) | ((uint64_t)1 << 63); }
+__device__ __forceinline__ int pair_t(uint64_t w) { return (int)(w & 2047u); }
+__device__ __forceinline__ int pair_row16(uint64_t w) { return (int)((w >> 11) & 4095u); }
+__device__ __forceinline__ double pair_x(uint64_t w)
+{
+    const uint64_t one_f = ((w >> 12) & ~(uint64_t)0x7FF) | 0x3FF0000000000000ull;   // 1 + f
+    return fma(2.0, __longlong_as_double((long long)one_f), -3.0);
+}
 
 // Work units (units with sources and with targets in their block), one record
 // of kCellRec int32 each: the unit's sources [s0, s1) in sorted order, then the
 // five runs (block rows) of its targets (rbeg[5], rcum[6]; see block_target).
 constexpr int kCellRec = kPairRec;
 
+// One item of the producer / consumer local kernel: the pair words [p0, p1) of one segment (a
+// source chunk [sb, sb + ns) of work unit wk against target batch b), whole runs of kRunPairs.
+// Each workgroup's items are consecutive (PairLists::ioff), the items of one (unit, batch)
+// consecutive among them.
+struct LpDesc {
+    int64_t p0, p1;
+    int32_t sb, ns, wk, b;
+};
+
 struct PairLists {
     const int32_t *wrec;          // [n_work][kCellRec]
     const int64_t *wseg;          // first segment of each work unit, [n_work + 1]
     int n_work;
     const int64_t *off, *doff;    // first pair of each (segment, source in chunk), [n_seg * kFastSrc + 1]
-    const int64_t *soff, *sdoff;  // first pair of each segment, [n_seg + 1]
     const uint64_t *pw;           // regular pairs (pair_pack)
     const uint32_t *dent;         // pairs with r < dt/2: t | s << 16
-    const double *dw;             //   and their weights eta_d(r), d < nlev (dyadic sub-panel tables)
+    const double *dw;             //   their weights eta_d(r), [nlev][ndy] (dyadic sub-panel tables)
+    const int32_t *dtg, *dsg;     //   their sorted target and source indices
+    int64_t ndy;
+    const LpDesc *desc;           // items of the producer / consumer kernel, by workgroup
+    const int32_t *ioff;          //   first item of each workgroup, [grid + 1]
 };
 
 struct PairBuild {
-    int64_t *cnt, *dcnt;          // count pass: pairs per (segment, source in chunk)
+    int64_t *cnt, *dcnt;          // count pass, per (segment, source in chunk): words | pairs << 32, dyadic pairs
     uint64_t *pw;                 // fill pass: the lists, at the offsets of PairLists
     uint32_t *dent;
-    double *dw;
+    double *dw;                   //   weights of the pairs with r < dt/2, [nlev][ndy]
+    int32_t *dtg, *dsg;           //   and their sorted target and source indices
+    int64_t ndy;
     int fill, nlev;
+    int psi_src, dterms;          // profile layout of the pair kernel (row offsets in the words)
 };
 
 // targets of a work unit's block: five runs of the sorted target order (rows
@@ -1332,15 +1402,20 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
             const int sl = task % kFastSrc, ib = task / kFastSrc, b = ib % nb, i = ib / nb;
             const int64_t slot = (seg0 + (int64_t)i * nb + b) * kFastSrc + sl;
             const int j = s0 + i * kFastSrc + sl;
-            int64_t c_reg = 0, c_dy = 0;
+            int64_t c_reg = 0, c_dy = 0, c_real = 0;
             if (j < s1) {
                 const double2 y = A.sxy[j];
                 const int tb0 = b * kPairTB, ntb = min(kPairTB, NT - tb0);
                 const int64_t o_reg = B.fill ? P.off[slot] : 0, o_dy = B.fill ? P.doff[slot] : 0;
+                // the fill pass writes the slot's regular pairs panel by panel (then in target
+                // order), so that a wave's consecutive pairs mostly share one profile row
+                for (int kk = 0; kk < W; ++kk) {
+                const int64_t c_start = c_reg;
                 for (int t0 = 0; t0 < ntb; t0 += 64) {
                     const int t = t0 + lane;
                     bool reg = false, dya = false;
-                    double r2 = 0.0;
+                    double r2 = 0.0, x = 0.0;
+                    int k = 0;
                     if (t < ntb) {
                         const double2 xt = A.txy[block_target(rbeg, rcum, tb0 + t)];
                         const double dx = xt.x - y.x, dy = xt.y - y.y;
@@ -1348,33 +1423,53 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
                         const bool hit = r2 > 0.0 && r2 < d2;
                         dya = hit && r2 < q2;
                         reg = hit && !dya;
+                        if (reg) {
+                            k = fast_panel(A, sqrt(r2), W, dt, x);
+                            reg = k == kk;
+                        }
+                        dya = dya && kk == 0;
                     }
                     const uint64_t mr = __ballot(reg), md = __ballot(dya);
                     if (B.fill && reg) {
                         const int64_t e = o_reg + c_reg + __popcll(mr & below);
-                        double x;
-                        const int k = fast_panel(A, sqrt(r2), W, dt, x);
-                        B.pw[e] = pair_pack(t, sl, k, x);
+                        B.pw[e] = pair_pack(t, (sl * B.psi_src + k * B.dterms) / 2, x);
                     }
                     if (B.fill && dya) {
                         const int64_t e = o_dy + c_dy + __popcll(md & below);
                         B.dent[e] = (uint32_t)t | ((uint32_t)sl << 16);
+                        B.dtg[e] = block_target(rbeg, rcum, tb0 + t);
+                        B.dsg[e] = j;
                         const double r = sqrt(r2);
                         const int sub = dyadic_sub(A, r * A.inv_dt);
                         const double xc = sub_coord(A.subs[sub], r);
                         for (int d = 0; d < B.nlev; ++d)
-                            B.dw[e * B.nlev + d] = cheb_eval(A.cheb + ((size_t)sub * B.nlev + d) * kChebDeg, xc);
+                            B.dw[d * B.ndy + e] = cheb_eval(A.cheb + ((size_t)sub * B.nlev + d) * kChebDeg, xc);
                     }
                     c_reg += __popcll(mr);
+                    c_real += __popcll(mr);
                     c_dy += __popcll(md);
+                }
+                // the panel's group padded to whole runs of kRunPairs (padding: the group's row, x = 0)
+                const int64_t padded = c_start + (c_reg - c_start + kRunPairs - 1) / kRunPairs * kRunPairs;
+                if (B.fill)
+                    for (int64_t e = c_reg + lane; e < padded; e += 64)
+                        B.pw[o_reg + e] = pair_pad(o_reg + e) | ((uint64_t)((sl * B.psi_src + kk * B.dterms) / 2) << 11);
+                c_reg = padded;
                 }
             }
             if (!B.fill && lane == 0) {
-                B.cnt[slot] = c_reg;
+                B.cnt[slot] = c_reg | c_real << 32;       // words (pairs and padding), pairs
                 B.dcnt[slot] = c_dy;
             }
         }
     }
+}
+
+// every pair word set to the padding entry of its position (the fill pass then writes the pairs)
+__global__ void k_pairs_pad(uint64_t *__restrict__ pw, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) pw[e] = pair_pad(e);
 }
 
 // a value the whole wave holds (loaded from LDS or memory), moved to a scalar register
@@ -1387,207 +1482,266 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// NL sigma levels; NTERM leading Chebyshev terms of each regular panel's series (of kChebDeg
-// stored), enough for the plan's tolerance; TPB threads per workgroup, 1024 / TPB workgroups per CU
-// (at least 4 waves per SIMD, so at most 128 VGPRs).
-// Software pipeline over the workgroup's chunks: while chunk i is synthesised and evaluated,
-// the sigma values and segment bounds of chunk i+1 are in flight (loaded right after chunk
-// i's sigma is stored, before anything that waits on memory), so the next chunk starts
-// without a memory wait.  sigma and the cell records are double-buffered in LDS.
-template <int NL, int NTERM, int TPB>
-__global__ __launch_bounds__(TPB, 4) void k_local_pairs(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
+// ---------------------------------------------------------------------------
+// Local part from the pair lists, producer / consumer form.  One workgroup of
+// 16 waves per CU walks its work items (work unit, target batch, source chunk:
+// a segment of the lists) in order.  The first nprod waves (producers)
+// synthesise the profile coefficients psi = C sigma of item t+1 with FP64 MFMA
+// into one of two LDS buffers while the other waves (consumers) evaluate the
+// pairs of item t from the other buffer, with the item's pair words loaded one
+// item ahead; one workgroup barrier per item.  Producers hold the MFMA A
+// operands and the sigma (B) operands in registers, consumers only pair words:
+// each role fits its registers, and the matrix units and the vector units work
+// at the same time.  Per-target sums of a (work unit, batch) collect in one of
+// two LDS buffers and are flushed to u_l with device atomics one item after
+// the batch ends (its buffer is then no longer written).  Pairs with
+// r < dt/2 are summed by k_local_dyadic.
+// ---------------------------------------------------------------------------
+// A uniform record spread over the lanes of one register (lane k holds 32-bit word k),
+// loaded ahead of use without tying up a register per word; fields are read with readlane.
+// (src is wave-uniform; every lane loads, lanes from nwords on the last word, so no branch
+// surrounds the load and no use of the value other than word32 / word64 waits for it)
+__device__ __forceinline__ uint32_t lane_words(const void *src, int nwords, int lane)
 {
-    constexpr int nwave = TPB / 64, KS = (NL + 3) / 4, NSIG = (kFastSrc * NL + TPB - 1) / TPB;
-    constexpr int D = NTERM, kRow = NTERM + 1;        // psi row stride (odd: rows spread over the LDS banks)
+    return reinterpret_cast<const uint32_t *>(src)[(uint32_t)min(lane, nwords - 1)];
+}
+__device__ __forceinline__ int word32(uint32_t v, int k) { return __builtin_amdgcn_readlane((int)v, k); }
+__device__ __forceinline__ int64_t word64(uint32_t v, int k)
+{
+    return (int64_t)(((uint64_t)(uint32_t)word32(v, k + 1) << 32) | (uint32_t)word32(v, k));
+}
+// LpDesc words: p0 = 0..1, p1 = 2..3, sb = 4, ns = 5, wk = 6, b = 7
+constexpr int kDescWords = 8;
+
+
+// RB 16-row MFMA blocks per producer wave; the A operands (the power-basis table) in registers
+// (RB == 2), in LDS (RB == 4: the table is staged once per launch), or read from cache (RB == 3).
+template <int NL, int NTERM, int RB>
+__global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g, int nprod,
+                                                   int nbmax)
+{
+    // Every global load is issued at least one item before its value is used, and the loop
+    // bodies have no data-dependent branches around loads or MFMAs, so the in-order wait on
+    // outstanding loads never waits for a prefetch of a later item.
+    constexpr int KS = (NL + 3) / 4, D = NTERM;
+    constexpr bool kRegA = RB == 2, kLdsA = RB == 4;
+    if (kLdsA) nprod = 4;                             // the LDS-table form always has four producers
     const int64_t m = step[0] - g.lookahead;
-    extern __shared__ double fast_lds[];              // psi [kFastSrc][psiSrc]
-    __shared__ double sigs[2][kFastSrc * NL];         // sigma of a chunk (buffer = chunk parity)
-    __shared__ double tacc[kPairTB];                  // per-target sums, zero between flushes
-    __shared__ int64_t slot_base[NL];                 // ring offset of sigma level d at this step
-    __shared__ int recs[2][kCellRec];                 // work-cell records (buffer = cell parity)
+    // dynamic LDS: [A table: kPcLdsRows x 4 KS (RB == 4)] then psi[2][kFastSrc][psiSrc] (16-byte rows)
+    extern __shared__ __align__(16) double lp_dyn[];
+    double *const ctab = lp_dyn;
+    double *const lp_lds = lp_dyn + (kLdsA ? kPcLdsRows * 4 * KS : 0);
+    __shared__ double tacc[2][kPairTBPad];            // per-target sums of a (unit, batch), by parity
 
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
-    const int nrow = A.n_reg * D, psiSrc = A.n_reg * kRow + 1;
-    const int nblk = (nrow + 15) / 16;
-    double *psi = fast_lds;
-    const int G = gridDim.x;
-    int wk = blockIdx.x;
-    if (wk >= P.n_work) return;                       // uniform, before any barrier
-
-    if (tid < NL) slot_base[tid] = sig_slot(m, tid, g) * g.M;
-    for (int t = tid; t < kPairTB; t += TPB) tacc[t] = 0.0;
-    if (tid < kCellRec) recs[0][tid] = P.wrec[(int64_t)wk * kCellRec + tid];
-    // A operands of this wave's row blocks of C (FP64 MFMA 16x16x4: lane holds
-    // C[rb*16 + lane%16][4 ks + lane/16]), loaded once and kept in registers
-    double ca[kPairRB][KS];
-#pragma unroll
-    for (int j = 0; j < kPairRB; ++j) {
-        const int row = (wave + j * nwave) * 16 + (lane & 15);
-        const int rr = min(row, nrow - 1);
-        const double *__restrict__ crow = A.creg + (size_t)((rr / D) * kChebDeg + rr % D) * NL;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int d = 4 * ks + (lane >> 4);
-            ca[j][ks] = (row < nrow && d < NL) ? crow[d] : 0.0;
+    const int nrow = A.n_reg * D, psiSrc = A.n_reg * D + 2;
+    const int i0 = P.ioff[blockIdx.x], ni = P.ioff[blockIdx.x + 1] - i0;   // this workgroup's items
+    const LpDesc *__restrict__ desc = P.desc + i0;
+    auto item = [&](int t) { return lane_words(desc + min(t, ni - 1), kDescWords, lane); };   // in range when ni > 0
+    for (int t = tid; t < 2 * kPairTBPad; t += 1024) (&tacc[0][0])[t] = 0.0;
+    if (kLdsA)                                        // A table C[row][d], rows past the table and d >= NL zero
+        for (int e = tid; e < kPcLdsRows * 4 * KS; e += 1024) {
+            const int row = e / (4 * KS), d = e - row * (4 * KS);
+            ctab[e] = (row < nrow && d < NL) ? A.cpow[(size_t)((row / D) * kChebDeg + row % D) * NL + d] : 0.0;
         }
-    }
     __syncthreads();
+    if (ni == 0) return;                              // uniform, after the only barrier so far
 
-    // the next chunk's sigma values (NSIG per thread) and batch-0 segment bounds
-    double sreg[NSIG];
-    int64_t np0 = 0, np1 = 0, nq0 = 0, nq1 = 0;
-    auto prefetch = [&](int sb, int ns, int64_t seg) {
+    if (wave < nprod) {
+        // ---------------- producer ----------------
+        // A operand of block r, step ks: C[row][d], row = (wave + r nprod) 16 + lane % 16, d = 4 ks + lane / 16
+        // (zero for rows past the table: their MFMAs add nothing and their rows are not stored)
+        auto a_op = [&](int r, int ks) {
+            const int row = (wave + r * nprod) * 16 + (lane & 15), d = 4 * ks + (lane >> 4);
+            if (kLdsA) return ctab[row * (4 * KS) + d];
+            const int rr = min(row, nrow - 1), dd = min(d, NL - 1);
+            const double v = A.cpow[(size_t)((rr / D) * kChebDeg + rr % D) * NL + dd];
+            return (row < nrow && d < NL) ? v : 0.0;
+        };
+        double ca[kRegA ? RB : 1][KS];
 #pragma unroll
-        for (int k = 0; k < NSIG; ++k) {
-            const int e = tid + k * TPB;
-            sreg[k] = 0.0;
-            if (e < ns * NL) {
-                const int sidx = e / NL, d = e - sidx * NL;
-                sreg[k] = A.sig[slot_base[d] + sb + sidx];
+        for (int r = 0; r < (kRegA ? RB : 0); ++r)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) ca[r][ks] = a_op(r, ks);
+        // B operands sigma[q][d] (q = lane % 16, d = 4 ks + lane / 16) of two items, loaded two
+        // items ahead.  A lane past the chunk loads the chunk's first source: its column of psi is
+        // never read.  A lane past the levels loads level NL - 1: its A column is zero, so it adds
+        // nothing (a non-finite sample there makes the result non-finite either way).
+        // The ring slot of level d is (s0 - d) mod depth with s0 the slot of level 0 (d < NL <= depth).
+        const int s0 = (int)sig_slot(m, 0, g), depth = (int)g.sig_depth;
+        double bva[KS], bvb[KS];
+        auto load_b = [&](double (&bv)[KS], uint32_t dv) {
+            const int sb = word32(dv, 4), ns = word32(dv, 5), q = lane & 15;
+            const int64_t src = sb + (q < ns ? q : 0);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int sl = s0 - min(4 * ks + (lane >> 4), NL - 1);
+                bv[ks] = A.sig[(int64_t)(sl < 0 ? sl + depth : sl) * g.M + src];
             }
-        }
-        if (ns > 0) {
-            np0 = P.soff[seg];
-            np1 = P.soff[seg + 1];
-            nq0 = P.sdoff[seg];
-            nq1 = P.sdoff[seg + 1];
-        }
-    };
-    int c_sb = uniform(recs[0][0]), c_ns = min(kFastSrc, uniform(recs[0][1]) - c_sb);
-    prefetch(c_sb, c_ns, uniform64(P.wseg[wk]));
-    int nrec = (tid < kCellRec && wk + G < P.n_work) ? P.wrec[(int64_t)(wk + G) * kCellRec + tid] : 0;
-    int par = 0;
-
-    // pair words and coordinates of a wave's next 128-pair block (loaded ahead of use)
-    uint64_t nw0 = 0u, nw1 = 0u;
-    auto fetch = [&](int64_t bs, int64_t pend) {
-        const int64_t e0 = bs + lane, e1 = e0 + 64;
-        nw0 = e0 < pend ? P.pw[e0] : 0u;
-        nw1 = e1 < pend ? P.pw[e1] : 0u;
-    };
-
-    for (int j = 0; wk < P.n_work; ++j, wk += G) {
-        const int *rec = recs[j & 1];
-        const int *rbeg = rec + 2, *rcum = rec + 7;
-        if (j > 0 && tid < kCellRec) {                // its buffer was last read two cells ago
-            recs[j & 1][tid] = nrec;
-            nrec = wk + G < P.n_work ? P.wrec[(int64_t)(wk + G) * kCellRec + tid] : 0;
-        }
-        const bool more = wk + G < P.n_work;
-        const int next_s0 = more ? uniform(P.wrec[(int64_t)(wk + G) * kCellRec]) : 0;
-        const int next_s1 = more ? uniform(P.wrec[(int64_t)(wk + G) * kCellRec + 1]) : 0;
-        const int64_t next_seg0 = more ? uniform64(P.wseg[wk + G]) : 0;
-        const int64_t seg0 = uniform64(P.wseg[wk]);
-        int nb = 1, NT = 0;
-        for (int i = 0;; ++i) {
-            const int sb = c_sb, ns = c_ns;
-            const int64_t p0 = uniform64(np0), p1 = uniform64(np1), q0 = uniform64(nq0), q1 = uniform64(nq1);
+        };
+        auto synth = [&](const double (&bv)[KS], double *dst) {
+            mfma_d4 acc[RB];
 #pragma unroll
-            for (int k = 0; k < NSIG; ++k) {
-                const int e = tid + k * TPB;
-                if (e < ns * NL) sigs[par][e] = sreg[k];
-            }
-            __syncthreads();                          // sigma and the record visible; psi free
-            const int s1 = uniform(rec[1]);
-            NT = uniform(rcum[5]);
-            nb = (NT + kPairTB - 1) / kPairTB;
-            const bool last = sb + ns >= s1;
-            int64_t nseg;
-            if (!last) {
-                c_sb = sb + kFastSrc;
-                c_ns = min(kFastSrc, s1 - c_sb);
-                nseg = seg0 + (int64_t)(i + 1) * nb;
-            } else {
-                c_sb = next_s0;
-                c_ns = more ? min(kFastSrc, next_s1 - next_s0) : 0;
-                nseg = next_seg0;
-            }
-            prefetch(c_sb, c_ns, nseg);
-            if (p0 + (int64_t)wave * 128 < p1) fetch(p0 + (int64_t)wave * 128, p1);   // first pair block of batch 0
-            {
-                // psi = C sigma
-                mfma_d4 acc[kPairRB];
+            for (int r = 0; r < RB; ++r) acc[r] = mfma_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < kPairRB; ++r) acc[r] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-                const int q = lane & 15;
+            for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int r = 0; r < kPairRB; ++r) {
-                    const int rb = wave + r * nwave;
-                    if (rb >= nblk) continue;              // uniform across the wave
+                for (int r = 0; r < RB; ++r)
+                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(kRegA ? ca[kRegA ? r : 0][ks] : a_op(r, ks), bv[ks], acc[r],
+                                                                  0, 0, 0);
+            // D[lane][e] = C[row = (wave + r nprod) 16 + lane / 16 + 4 e][q = lane % 16]; with nprod
+            // known at compile time the stores share one address register and immediate offsets
+            double *const dq = dst + (lane & 15) * psiSrc + wave * 16 + (lane >> 4);
 #pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) {
-                        const int d = 4 * ks + (lane >> 4);
-                        const double b = (q < ns && d < NL) ? sigs[par][q * NL + d] : 0.0;   // B[d][q] = sigma_{q,d}
-                        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[r][ks], b, acc[r], 0, 0, 0);
-                    }
-                }
+            for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int r = 0; r < kPairRB; ++r) {
-                    const int rb = wave + r * nwave;
-                    if (rb >= nblk || q >= ns) continue;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int row = rb * 16 + (lane >> 4) + 4 * e;   // D[lane][e] = C[lane/16 + 4 e][lane%16]
-                        if (row < nrow) psi[q * psiSrc + (row / D) * kRow + row % D] = acc[r][e];
-                    }
-                }
-            }
-            __syncthreads();                          // psi visible
-            for (int b = 0; b < nb; ++b) {
-                const int64_t seg = seg0 + (int64_t)i * nb + b;
-                const int64_t bp0 = b ? uniform64(P.soff[seg]) : p0, bp1 = b ? uniform64(P.soff[seg + 1]) : p1;
-                const int64_t stride = (int64_t)nwave * 128;
-                int64_t base = bp0 + (int64_t)wave * 128;
-                if (b && base < bp1) fetch(base, bp1);
-                for (; base < bp1; base += stride) {
-                    const uint64_t w0 = nw0, w1 = nw1;
-                    const bool v0 = base + lane < bp1, v1 = base + 64 + lane < bp1;
-                    if (base + stride < bp1) fetch(base + stride, bp1);
-                    double u0, u1;
-                    cheb_eval2n<D>(psi + pair_s(w0) * psiSrc + pair_k(w0) * kRow, pair_x(w0),
-                                   psi + pair_s(w1) * psiSrc + pair_k(w1) * kRow, pair_x(w1), u0, u1);
-                    // padding lanes add 0 to distinct sums (no same-address atomics, and no branch
-                    // around the two sums, which would then be evaluated one after the other)
-                    atomicAdd(&tacc[v0 ? pair_t(w0) : lane], v0 ? u0 : 0.0);
-                    atomicAdd(&tacc[v1 ? pair_t(w1) : 64 + lane], v1 ? u1 : 0.0);
-                }
-                // pairs with r < dt/2: one lane per pair, sum over levels with the stored weights
-                const int64_t bq0 = b ? uniform64(P.sdoff[seg]) : q0, bq1 = b ? uniform64(P.sdoff[seg + 1]) : q1;
-                for (int64_t q = bq0 + (int64_t)wave * 64 + lane; q < bq1; q += (int64_t)nwave * 64) {
-                    const uint32_t wq = P.dent[q];
-                    const double *__restrict__ wd = P.dw + q * NL;
-                    const double *sg = sigs[par] + (int)((wq >> 16) & 15u) * NL;
-                    double v = 0.0;
-#pragma unroll 5
-                    for (int d = 0; d < NL; ++d) v = fma(wd[d], sg[d], v);
-                    atomicAdd(&tacc[wq & 0xffffu], v);
-                }
-                if (nb > 1) {                         // several target batches: flush each
-                    const int tb0 = b * kPairTB, ntb = min(kPairTB, NT - tb0);
-                    __syncthreads();
-                    for (int t = tid; t < ntb; t += TPB) {
-                        const double v = tacc[t];
-                        if (v != 0.0) {
-                            unsafeAtomicAdd(&A.ul[block_target(rbeg, rcum, tb0 + t)], v);
-                            tacc[t] = 0.0;
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            par ^= 1;
-            if (last) break;
-        }
-        if (nb == 1) {                                // one batch: the sums of the whole cell
+                for (int e = 0; e < 4; ++e)
+                    if ((lane >> 4) < nrow - (wave + r * nprod) * 16 - 4 * e) dq[r * nprod * 16 + 4 * e] = acc[r][e];
+        };
+        load_b(bva, item(0));
+        synth(bva, lp_lds);                           // item 0 -> buffer 0
+        load_b(bva, item(1));
+        load_b(bvb, item(2));
+        uint32_t d3 = item(3);                        // descriptor of the next item whose sigma is loaded
+        __syncthreads();
+        // item t: synthesise item t + 1 from the registers loaded two items ago (bva for even t,
+        // bvb for odd t), then load item t + 3's sigma into them (clamped at the last item)
+        auto iter = [&](double (&bv)[KS], int t) {
+            synth(bv, lp_lds + (size_t)((t + 1) & 1) * kFastSrc * psiSrc);   // past the last item: unused
+            const uint32_t dv = d3;
+            d3 = item(t + 4);
+            load_b(bv, dv);
             __syncthreads();
-            for (int t = tid; t < NT; t += TPB) {
-                const double v = tacc[t];
-                if (v != 0.0) {
-                    unsafeAtomicAdd(&A.ul[block_target(rbeg, rcum, t)], v);
-                    tacc[t] = 0.0;
-                }
+        };
+        for (int t = 0; t < ni; t += 2) {
+            iter(bva, t);
+            if (t + 1 < ni) iter(bvb, t + 1);
+        }
+        return;
+    }
+
+    // ---------------- consumer ----------------
+    // Lane cl of the consumers takes run cl of the item (words p0 + kRunPairs cl, ...): its pairs
+    // share one profile row, loaded once into registers; the run's pairs are independent Horner
+    // chains.  The next item's run is loaded during this one; runs past the consumers' lanes
+    // (items of more runs) follow from memory.
+    const int cw = wave - nprod, ncons = 16 - nprod, nl = ncons * 64, cl = cw * 64 + lane;
+    // the (unit, batch) whose sums are in tacc[(sub - 1) & 1]; its predecessor is flushed one item later
+    int sub = 0, pwk = -1, pb = 0;
+    uint32_t prec = 0u;                               // record of the (unit, batch) being summed (lane words)
+    // (a fixed number of predicated atomics per lane, so that the compiler's count of
+    // outstanding memory operations stays exact across the loop)
+    auto flush = [&](int buf, int fb, uint32_t rec) {
+        int rbeg[5], rcum[6];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) rbeg[k] = word32(rec, 2 + k);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) rcum[k] = word32(rec, 7 + k);
+        const int tb0 = fb * kPairTB, ntb = min(kPairTB, rcum[5] - tb0);
+#pragma unroll
+        for (int k = 0; k < kPcFlushRounds; ++k) {
+            const int t = cl + k * nl;
+            const double v = t < ntb ? tacc[buf][t] : 0.0;
+            if (v != 0.0) {
+                unsafeAtomicAdd(&A.ul[block_target(rbeg, rcum, tb0 + t)], v);
+                tacc[buf][t] = 0.0;
             }
         }
+    };
+    // run r of the item [p0, p1) (p0, p1 uniform; an item holds fewer than 2^28 runs); a lane
+    // past the item's runs loads run 0 (word 0 of the lists if the item is empty), and its sums
+    // go to the padding entries.  The loads are unconditional.
+    auto load_run = [&](uint64_t (&w)[kRunPairs], int64_t p0, int64_t p1, int r) {
+        const uint64_t *base = P.pw + (p1 > p0 ? p0 : 0);
+        const uint32_t e0 = (int64_t)kRunPairs * r < p1 - p0 ? (uint32_t)(kRunPairs * r) : 0u;
+#pragma unroll
+        for (int j = 0; j < kRunPairs; ++j) w[j] = base[e0 + (uint32_t)j];
+    };
+    auto run = [&](const uint64_t (&w)[kRunPairs], bool ok, const double2 *ps, double *acc) {
+        const double2 *row = ps + pair_row16(w[0]);
+        double2 c[D / 2];
+#pragma unroll
+        for (int j = 0; j < D / 2; ++j) c[j] = row[j];
+        // two halves of four chains each (the scheduler barrier keeps their registers apart)
+#pragma unroll
+        for (int h = 0; h < kRunPairs; h += kRunPairs / 2) {
+            double x[kRunPairs / 2], y[kRunPairs / 2];
+#pragma unroll
+            for (int i = 0; i < kRunPairs / 2; ++i) {
+                x[i] = pair_x(w[h + i]);
+                y[i] = fma(c[D / 2 - 1].y, x[i], c[D / 2 - 1].x);
+            }
+#pragma unroll
+            for (int j = D / 2 - 2; j >= 0; --j)
+#pragma unroll
+                for (int i = 0; i < kRunPairs / 2; ++i) y[i] = fma(fma(y[i], x[i], c[j].y), x[i], c[j].x);
+#pragma unroll
+            for (int i = 0; i < kRunPairs / 2; ++i)
+                atomicAdd(&acc[ok ? pair_t(w[h + i]) : kPairTB + h + i], y[i]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // item t with its run wc, descriptor dc and unit record rc, all loaded during item t - 1; it
+    // loads item t + 1's run and record into wn and rn, and item t + 2's descriptor into dc.  The
+    // loop runs two items per pass with the registers' roles swapped, so that no loaded value is
+    // copied (a copy would wait for every load issued before it).
+    auto iter = [&](uint64_t (&wc)[kRunPairs], uint64_t (&wn)[kRunPairs], uint32_t &dc, uint32_t dn, uint32_t rc,
+                    uint32_t &rn, int t) {
+        const int64_t p0 = word64(dc, 0), p1 = word64(dc, 2);
+        const int wk = word32(dc, 6), b = word32(dc, 7);
+        const int64_t q0 = word64(dn, 0), q1 = word64(dn, 2);
+        const int wkn = word32(dn, 6);
+        const bool fresh = wk != pwk || b != pb;      // a new (unit, batch) starts with this item
+        // the previous (unit, batch), all its items summed, is flushed after the last wait for
+        // loads of the previous item and before this item's loads are issued, so that the next
+        // wait (for those loads) finds the atomics long done
+        if (fresh && pwk >= 0) flush((sub - 1) & 1, pb, prec);
+        load_run(wn, q0, q1, cl);                     // in flight during this item
+        rn = lane_words(P.wrec + (int64_t)wkn * kCellRec, 13, lane);
+        dc = item(t + 2);
+        if (fresh) {
+            prec = rc;
+            pwk = wk;
+            pb = b;
+            sub += 1;
+        }
+        double *acc = tacc[(sub - 1) & 1];
+        const double2 *ps = reinterpret_cast<const double2 *>(lp_lds + (size_t)(t & 1) * kFastSrc * psiSrc);
+        if (kRunPairs * (int64_t)(cw * 64) < p1 - p0)                      // waves past the item's runs idle
+            run(wc, (int64_t)kRunPairs * cl < p1 - p0, ps, acc);
+        for (int r = cl + nl; (int64_t)kRunPairs * r < p1 - p0; r += nl) {   // items of more runs than consumer lanes
+            uint64_t w[kRunPairs];
+#pragma unroll
+            for (int j = 0; j < kRunPairs; ++j) w[j] = P.pw[p0 + (uint32_t)(kRunPairs * r + j)];
+            run(w, true, ps, acc);
+        }
+        __syncthreads();
+    };
+    uint64_t wa[kRunPairs], wb[kRunPairs];
+    uint32_t da = item(0), db = item(1);
+    uint32_t ra = lane_words(P.wrec + (int64_t)word32(da, 6) * kCellRec, 13, lane), rb = 0u;
+    load_run(wa, word64(da, 0), word64(da, 2), cl);
+    __syncthreads();                                  // psi of item 0 is ready
+    for (int t = 0; t < ni; t += 2) {
+        iter(wa, wb, da, db, ra, rb, t);              // da <- item t + 2
+        if (t + 1 < ni) iter(wb, wa, db, da, rb, ra, t + 1);   // db <- item t + 3
+    }
+    if (pwk >= 0) flush((sub - 1) & 1, pb, prec);     // the last (unit, batch): all items summed
+}
+
+// Pairs with r < dt/2 (their stored weights over the sigma levels), one lane per pair.
+__global__ __launch_bounds__(256) void k_local_dyadic(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g)
+{
+    __shared__ int64_t slot_base[kLocalMaxLevels];
+    const int64_t m = step[0] - g.lookahead;
+    if ((int)threadIdx.x < g.nlev) slot_base[threadIdx.x] = sig_slot(m, threadIdx.x, g) * g.M;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P.ndy; q += stride) {
+        const int s = P.dsg[q];
+        double v = 0.0;
+        for (int d = 0; d < g.nlev; ++d) v = fma(P.dw[(int64_t)d * P.ndy + q], A.sig[slot_base[d] + s], v);
+        unsafeAtomicAdd(&A.ul[P.dtg[q]], v);
     }
 }
 
@@ -1675,27 +1829,24 @@ hipError_t launch_spread(Plan &p)
     return p.precision == WFP2D_PREC_MIXED ? spread_typed<float>(p) : spread_typed<double>(p);
 }
 
-// dynamic LDS of the fast local kernel: up to kFastRow rows x kFastSrc sources of
-// profile coefficients plus one hit ring per wave
+// dynamic LDS of the local kernels: the fast one's kFastRow rows x kFastSrc sources of profile
+// coefficients plus one hit ring per wave; the pair-list one's two profile buffers
 hipError_t kernel_setup(Plan &)
 {
     const int bytes = kFastSrc * (kFastRow / kChebDeg * (kChebDeg + 1) + 1) * (int)sizeof(double) +
                       (kFastRow / 64) * kFastRing * 12;
-    const int pbytes = kFastSrc * (kFastRow / kChebDeg * (kChebDeg + 1) + 1) * (int)sizeof(double);
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_local_fast<35>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
     if ((e = hipFuncSetAttribute((const void *)k_local_fast<43>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes))) return e;
-    const void *pk[] = {
-#define WFP2D_PAIR_KERNELS(NLV) \
-        (const void *)k_local_pairs<NLV, 12, kPairThreadsHalf>, (const void *)k_local_pairs<NLV, 14, kPairThreadsHalf>, \
-        (const void *)k_local_pairs<NLV, 16, kPairThreadsHalf>, (const void *)k_local_pairs<NLV, 12, kPairThreads>, \
-        (const void *)k_local_pairs<NLV, 14, kPairThreads>, (const void *)k_local_pairs<NLV, 16, kPairThreads>, \
-        (const void *)k_local_pairs<NLV, 20, kPairThreads>
-        WFP2D_PAIR_KERNELS(35), WFP2D_PAIR_KERNELS(43)
-#undef WFP2D_PAIR_KERNELS
-    };
-    for (const void *k : pk)
-        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, pbytes))) return e;
+    // producer / consumer kernel: two profile buffers and two pair-word buffers (the LDS left)
+    const int pcbytes = (int)kPcDynLds;
+    const void *pc[] = {(const void *)k_local_pc<35, 12, 2>, (const void *)k_local_pc<35, 14, 2>, (const void *)k_local_pc<35, 16, 2>,
+                        (const void *)k_local_pc<35, 20, 2>, (const void *)k_local_pc<43, 12, 2>, (const void *)k_local_pc<43, 14, 2>,
+                        (const void *)k_local_pc<43, 16, 2>, (const void *)k_local_pc<43, 20, 2>, (const void *)k_local_pc<35, 20, 3>,
+                        (const void *)k_local_pc<43, 20, 3>, (const void *)k_local_pc<35, 12, 4>,
+                        (const void *)k_local_pc<35, 14, 4>, (const void *)k_local_pc<35, 16, 4>};
+    for (const void *k : pc)
+        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, pcbytes))) return e;
     return hipSuccess;
 }
 
@@ -1852,6 +2003,7 @@ static LocalArgs local_args(const Plan &p)
     A.subs = p.d_subs;
     A.cheb = p.d_cheb;
     A.creg = p.d_creg;
+    A.cpow = p.d_cpow;
     A.pbase = p.d_panel_base;
     A.pl2n = p.d_panel_l2n;
     A.sig = p.d_sig;
@@ -1876,11 +2028,14 @@ static PairLists pair_lists(const Plan &p)
     P.n_work = (int)p.pair_n_work;
     P.off = p.d_pair_off;
     P.doff = p.d_pair_doff;
-    P.soff = p.d_seg_off;
-    P.sdoff = p.d_seg_doff;
     P.pw = p.d_pair_pw;
     P.dent = p.d_pair_dent;
     P.dw = p.d_pair_dw;
+    P.dtg = p.d_pair_dtg;
+    P.dsg = p.d_pair_dsg;
+    P.ndy = p.pair_ndy;
+    P.desc = (const LpDesc *)p.d_pc_desc;
+    P.ioff = p.d_pc_ioff;
     return P;
 }
 
@@ -1894,10 +2049,24 @@ hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt)
     B.pw = p.d_pair_pw;
     B.dent = p.d_pair_dent;
     B.dw = p.d_pair_dw;
+    B.dtg = p.d_pair_dtg;
+    B.dsg = p.d_pair_dsg;
+    B.ndy = p.pair_ndy;
+    B.psi_src = p.n_reg * p.local_terms + 2;
+    B.dterms = p.local_terms;
     B.fill = fill ? 1 : 0;
     B.nlev = p.g.nlev;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, 4096));
+    if (fill) hipLaunchKernelGGL(k_pairs_pad, dim3(4096), dim3(256), 0, p.stream, p.d_pair_pw, p.pair_nword);
     hipLaunchKernelGGL(k_pairs_build, dim3(grid), dim3(256), 0, p.stream, A, P, B, p.dt, (int)p.W);
+    return hipGetLastError();
+}
+
+static hipError_t launch_local_dyadic(Plan &p, const LocalArgs &A)
+{
+    if (p.pair_ndy == 0) return hipGetLastError();
+    const unsigned grid = (unsigned)std::min<int64_t>((p.pair_ndy + 255) / 256, (int64_t)p.n_cu * 8);
+    hipLaunchKernelGGL(k_local_dyadic, dim3(grid), dim3(256), 0, p.stream, A, pair_lists(p), p.d_step, p.g);
     return hipGetLastError();
 }
 
@@ -1905,27 +2074,33 @@ hipError_t launch_local(Plan &p)
 {
     const LocalArgs A = local_args(p);
     if (p.local_pairs) {
-        const int nrow = p.n_reg * p.local_terms;
-        // two 8-wave workgroups per CU (their phases overlap) when 8 waves cover the coefficient
-        // rows, else one 16-wave workgroup per CU
-        const bool half = p.local_terms < kChebDeg && nrow <= kPairThreadsHalf / 64 * kPairRB * 16;
-        const unsigned threads = half ? kPairThreadsHalf : kPairThreads;
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, (int64_t)p.n_cu * (half ? 2 : 1)));
-        const size_t lds = (size_t)kFastSrc * (p.n_reg * (p.local_terms + 1) + 1) * sizeof(double);
+        int rb = 2;
+        const int nprod = pc_producers(p.n_reg, p.local_terms, &rb, p.g.nlev);
+        const unsigned grid = (unsigned)p.pc_grid;
+        const int nbmax = 0;
+        const size_t lds = (size_t)2 * kFastSrc * (p.n_reg * p.local_terms + 2) * sizeof(double) +
+                           (rb == 4 ? (size_t)kPcLdsRows * 4 * ((p.g.nlev + 3) / 4) * sizeof(double) : 0);
         const PairLists P = pair_lists(p);
-#define WFP2D_LAUNCH_PAIRS(NLV, NTV, TPB) \
-    hipLaunchKernelGGL((k_local_pairs<NLV, NTV, TPB>), dim3(grid), dim3(threads), lds, p.stream, A, P, p.d_step, p.g)
-#define WFP2D_LAUNCH_PAIRS_NL(NTV, TPB) \
-    do { if (p.g.nlev == 35) WFP2D_LAUNCH_PAIRS(35, NTV, TPB); else WFP2D_LAUNCH_PAIRS(43, NTV, TPB); } while (0)
-        switch (p.local_terms) {
-        case 12: if (half) WFP2D_LAUNCH_PAIRS_NL(12, kPairThreadsHalf); else WFP2D_LAUNCH_PAIRS_NL(12, kPairThreads); break;
-        case 14: if (half) WFP2D_LAUNCH_PAIRS_NL(14, kPairThreadsHalf); else WFP2D_LAUNCH_PAIRS_NL(14, kPairThreads); break;
-        case 16: if (half) WFP2D_LAUNCH_PAIRS_NL(16, kPairThreadsHalf); else WFP2D_LAUNCH_PAIRS_NL(16, kPairThreads); break;
-        default: WFP2D_LAUNCH_PAIRS_NL(20, kPairThreads); break;
+#define WFP2D_LAUNCH_PC(NLV, NTV, RBV) \
+    hipLaunchKernelGGL((k_local_pc<NLV, NTV, RBV>), dim3(grid), dim3(1024), lds, p.stream, A, P, p.d_step, p.g, nprod, nbmax)
+#define WFP2D_LAUNCH_PC_NL(NTV, RBV) \
+    do { if (p.g.nlev == 35) WFP2D_LAUNCH_PC(35, NTV, RBV); else WFP2D_LAUNCH_PC(43, NTV, RBV); } while (0)
+        if (rb == 4 && p.local_terms == 16) WFP2D_LAUNCH_PC(35, 16, 4);
+        else if (rb == 4 && p.local_terms == 14) WFP2D_LAUNCH_PC(35, 14, 4);
+        else if (rb == 4) WFP2D_LAUNCH_PC(35, 12, 4);
+        else switch (p.local_terms) {
+        case 12: WFP2D_LAUNCH_PC_NL(12, 2); break;
+        case 14: WFP2D_LAUNCH_PC_NL(14, 2); break;
+        case 16: WFP2D_LAUNCH_PC_NL(16, 2); break;
+        default:
+            if (rb == 2) WFP2D_LAUNCH_PC_NL(20, 2);
+            else WFP2D_LAUNCH_PC_NL(20, 3);
+            break;
         }
-#undef WFP2D_LAUNCH_PAIRS_NL
-#undef WFP2D_LAUNCH_PAIRS
-        return hipGetLastError();
+#undef WFP2D_LAUNCH_PC_NL
+#undef WFP2D_LAUNCH_PC
+        hipError_t e = hipGetLastError();
+        return e != hipSuccess ? e : launch_local_dyadic(p, A);
     }
     if (p.local_fast) {
         const int nrow = p.n_reg * kChebDeg;

@@ -421,6 +421,48 @@ void local_table_eval(const LocalTable &T, double dt, int W, double r, double *o
     for (int d = 0; d < T.nlev; ++d) out[d] = cheb_eval(&T.coef[((size_t)sub * T.nlev + d) * kChebDeg], nt, xc);
 }
 
+void cheb_to_power(const double *b, int nt, double *a)
+{
+    // rows of integer coefficients: t_prev = T_{j-1}, t_cur = T_j (exact in int64 for j < 62)
+    std::vector<int64_t> t_prev(nt, 0), t_cur(nt, 0), t_next(nt, 0);
+    for (int c = 0; c < nt; ++c) a[c] = 0.0;
+    t_cur[0] = 1;                                   // T_0
+    for (int j = 0; j < nt; ++j) {
+        for (int c = 0; c <= j; ++c) a[c] += b[j] * (double)t_cur[c];
+        // T_{j+1} = 2x T_j - T_{j-1} (T_1 = x)
+        for (int c = 0; c < nt; ++c) {
+            const int64_t up = c > 0 ? t_cur[c - 1] : 0;
+            t_next[c] = (j == 0 ? 1 : 2) * up - (j == 0 ? 0 : t_prev[c]);
+        }
+        t_prev.swap(t_cur);
+        t_cur.swap(t_next);
+    }
+}
+
+void local_table_eval_power(const LocalTable &T, double dt, int W, double r, double *out, int nterm_regular)
+{
+    const double rr = r / dt;
+    if (rr < 0.5) {
+        local_table_eval(T, dt, W, r, out, nterm_regular);
+        return;
+    }
+    const int k = std::min((int)rr, W - 1);
+    const double lo = k == 0 ? 0.5 : (double)k, wd = k == 0 ? 0.5 : 1.0;
+    const int ns = 1 << T.panel_l2n[k];
+    const int sub = T.panel_base[k] + std::min((int)((rr - lo) / wd * ns), ns - 1);
+    const SubPanel &sp = T.subs[sub];
+    const double v = sp.c > 0.0 ? std::sqrt(std::max(0.0, sp.c - r)) : r;
+    const double xc = std::min(1.0, std::max(-1.0, (2.0 * v - sp.ua - sp.ub) * sp.inv));
+    const int nt = std::min(std::max(nterm_regular, 1), kChebDeg);
+    double a[kChebDeg];
+    for (int d = 0; d < T.nlev; ++d) {
+        cheb_to_power(&T.coef[((size_t)sub * T.nlev + d) * kChebDeg], nt, a);
+        double y = a[nt - 1];
+        for (int c = nt - 2; c >= 0; --c) y = std::fma(y, xc, a[c]);
+        out[d] = y;
+    }
+}
+
 int local_table_terms(const LocalTable &T, double tol, double *tail_out, double *cmax_out)
 {
     const int nl = T.nlev, D = kChebDeg;

@@ -67,6 +67,14 @@ void local_table_eval(const LocalTable &T, double dt, int W, double r, double *o
 // [-1, 1], that bound also bounds the change of every eta_d.  tail_out and cmax_out (if not
 // NULL) receive the bound for the returned count and the largest coefficient.
 int local_table_terms(const LocalTable &T, double tol, double *tail_out = nullptr, double *cmax_out = nullptr);
+// Power-basis form of a truncated Chebyshev series on [-1, 1]: a[c] (c < nt) with
+// sum_{j<nt} b[j] T_j(x) = sum_{c<nt} a[c] x^c, from the integer coefficients of T_j
+// (T_0 = 1, T_1 = x, T_{j+1} = 2x T_j - T_{j-1}).
+void cheb_to_power(const double *b, int nt, double *a);
+// eta_d(r) as the pair-list local kernel evaluates it: the regular sub-panels' series
+// truncated to nterm_regular terms and summed in the power basis by Horner's rule
+// (the dyadic sub-panels as local_table_eval).
+void local_table_eval_power(const LocalTable &T, double dt, int W, double r, double *out, int nterm_regular);
 
 double es_kernel(double z, int w, double beta);
 void es_fourier(int w, double beta, int64_t nf, int64_t R, std::vector<double> &out);

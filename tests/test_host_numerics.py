@@ -189,3 +189,46 @@ def test_local_tables_match_direct_quadrature(dt, W, p):
     top = mag[r >= 0.5 * dt].max()
     scale = np.array([max(mag[panel == k].max(), 1e-2 * top) for k in panel])[:, None]
     assert np.max(np.abs(table - direct) / scale) < 1e-11
+
+
+@pytest.mark.parametrize("terms", [12, 16, 20])
+def test_power_basis_weights_equal_the_truncated_chebyshev_series(terms):
+    """The pair kernel sums each regular panel's truncated Chebyshev series in the power
+    basis (Horner).  The same polynomial: it must agree with the Chebyshev evaluation of the
+    same terms to rounding, and with the direct quadrature of the weights (Sec. 6,
+    eq. ul_GL with eq. sigInterp) to the truncation level."""
+    import paper_2604_07170_amd as pa
+    dt, W, p, look, tol = 8.0 / 7150.0, 16, 20, -1, 1e-7
+    rng = np.random.default_rng(9)
+    r = np.sort(rng.uniform(0.5 * dt, W * dt * 0.999, size=40))
+    nl = 35
+    power = pa.host_eval(10, [dt, W, p, look, tol, terms] + list(r), len(r) * nl).reshape(len(r), nl)
+    direct = pa.host_eval(4, [dt, W, p, look, tol] + list(r), len(r) * nl).reshape(len(r), nl)
+    scale = np.abs(direct).max()
+    if terms == 20:
+        # every stored term: the table itself (fit error <= 1e-11 of the largest weight)
+        assert np.abs(power - direct).max() <= 1e-10 * scale
+    else:
+        # the dropped Chebyshev terms bound the difference (each |T_j| <= 1)
+        assert np.abs(power - direct).max() <= 1e-4 * scale
+    # Chebyshev form of the same truncation (host_eval 8 uses the plan's own term count;
+    # compare at that count)
+    out8 = pa.host_eval(8, [dt, W, p, look, tol] + list(r), 3 + len(r) * nl)
+    t8 = int(out8[0])
+    cheb = out8[3:].reshape(len(r), nl)
+    if t8 == terms:
+        assert np.abs(power - cheb).max() <= 1e-13 * scale
+
+
+def test_power_basis_with_every_term_matches_the_chebyshev_table():
+    """With all 20 stored terms (FP64 plans) the power-basis weights equal the Chebyshev
+    table's (host_eval 5) to rounding: the conversion loses no accuracy (measured 1.7e-16
+    of the largest weight; 16 terms against the 16-term Chebyshev sum likewise)."""
+    import paper_2604_07170_amd as pa
+    dt, W, p, tol = 8.0 / 7150.0, 16, 20, 1e-7
+    rng = np.random.default_rng(10)
+    r = np.sort(rng.uniform(0.5 * dt, W * dt * 0.999, size=25))
+    nl = 35
+    power = pa.host_eval(10, [dt, W, p, -1, tol, 20] + list(r), len(r) * nl).reshape(len(r), nl)
+    cheb = pa.host_eval(5, [dt, W, p, -1, tol] + list(r), len(r) * nl).reshape(len(r), nl)
+    assert np.abs(power - cheb).max() <= 1e-12 * np.abs(cheb).max()
