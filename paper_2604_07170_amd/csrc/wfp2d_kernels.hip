@@ -1314,7 +1314,10 @@ static_assert(kFastSrc <= 16 && kPairTB <= 1024, "pair words hold the target in 
 // resolution 9.1e-13), which under the exponent bits of 1.0 is the double 1 + f.
 // Within a slot the pairs of each panel are padded to whole runs of kRunPairs with padding
 // entries (target 1024 + e mod 128, the panel's profile row, x = 0), which add to private sums
-// past the targets': every run of an item's list shares one profile row.
+// past the targets': every run of an item's list shares one profile row.  A segment's runs are
+// stored interleaved by 16-byte chunks: chunk c (words 2c, 2c + 1) of run r of a segment of R
+// runs at 16-byte offset c R + r, so that the lanes of a wave, one run each, read each chunk
+// as one contiguous span.
 constexpr int kRunPairs = 8;
 constexpr int kPcFlushRounds = (kPairTB + 255) / 256;   // flush rounds of the local kernel's consumers (at least 4 waves)
 constexpr int kPairTBPad = kPairTB + 128;             // per-target sums plus the padding entries' sums
@@ -1325,6 +1328,13 @@ __device__ __forceinline__ uint64_t pair_pack(int t, int row16, double x)
     return (uint64_t)t | ((uint64_t)row16 << 11) | (q << 23);
 }
 __device__ __forceinline__ uint64_t pair_pad(int64_t e) { return (uint64_t)(1024 + (e & 127)) | ((uint64_t)1 << 63); }
+// storage index of word e (in run order) of a segment of nrun runs starting at word s0
+__device__ __forceinline__ int64_t pair_pos(int64_t s0, int64_t nrun, int64_t e)
+{
+    const int64_t rel = e - s0, r = rel / kRunPairs;
+    const int j = (int)(rel - r * kRunPairs);
+    return s0 + (int64_t)(j >> 1) * 2 * nrun + 2 * r + (j & 1);
+}
 __device__ __forceinline__ int pair_t(uint64_t w) { return (int)(w & 2047u); }
 __device__ __forceinline__ int pair_row16(uint64_t w) { return (int)((w >> 11) & 4095u); }
 __device__ __forceinline__ double pair_x(uint64_t w)
@@ -1407,6 +1417,8 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
                 const double2 y = A.sxy[j];
                 const int tb0 = b * kPairTB, ntb = min(kPairTB, NT - tb0);
                 const int64_t o_reg = B.fill ? P.off[slot] : 0, o_dy = B.fill ? P.doff[slot] : 0;
+                const int64_t seg = slot / kFastSrc, sg0 = B.fill ? P.off[seg * kFastSrc] : 0;
+                const int64_t nrun = B.fill ? (P.off[(seg + 1) * kFastSrc] - sg0) / kRunPairs : 0;
                 // the fill pass writes the slot's regular pairs panel by panel (then in target
                 // order), so that a wave's consecutive pairs mostly share one profile row
                 for (int kk = 0; kk < W; ++kk) {
@@ -1432,7 +1444,7 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
                     const uint64_t mr = __ballot(reg), md = __ballot(dya);
                     if (B.fill && reg) {
                         const int64_t e = o_reg + c_reg + __popcll(mr & below);
-                        B.pw[e] = pair_pack(t, (sl * B.psi_src + k * B.dterms) / 2, x);
+                        B.pw[pair_pos(sg0, nrun, e)] = pair_pack(t, (sl * B.psi_src + k * B.dterms) / 2, x);
                     }
                     if (B.fill && dya) {
                         const int64_t e = o_dy + c_dy + __popcll(md & below);
@@ -1453,7 +1465,8 @@ __global__ __launch_bounds__(256) void k_pairs_build(LocalArgs A, PairLists P, P
                 const int64_t padded = c_start + (c_reg - c_start + kRunPairs - 1) / kRunPairs * kRunPairs;
                 if (B.fill)
                     for (int64_t e = c_reg + lane; e < padded; e += 64)
-                        B.pw[o_reg + e] = pair_pad(o_reg + e) | ((uint64_t)((sl * B.psi_src + kk * B.dterms) / 2) << 11);
+                        B.pw[pair_pos(sg0, nrun, o_reg + e)] =
+                            pair_pad(o_reg + e) | ((uint64_t)((sl * B.psi_src + kk * B.dterms) / 2) << 11);
                 c_reg = padded;
                 }
             }
@@ -1652,10 +1665,14 @@ __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, con
     // past the item's runs loads run 0 (word 0 of the lists if the item is empty), and its sums
     // go to the padding entries.  The loads are unconditional.
     auto load_run = [&](uint64_t (&w)[kRunPairs], int64_t p0, int64_t p1, int r) {
-        const uint64_t *base = P.pw + (p1 > p0 ? p0 : 0);
-        const uint32_t e0 = (int64_t)kRunPairs * r < p1 - p0 ? (uint32_t)(kRunPairs * r) : 0u;
+        const ulonglong2 *base = reinterpret_cast<const ulonglong2 *>(P.pw + (p1 > p0 ? p0 : 0));
+        const uint32_t nrun = (uint32_t)((p1 - p0) / kRunPairs), rr = (uint32_t)r < nrun ? (uint32_t)r : 0u;
 #pragma unroll
-        for (int j = 0; j < kRunPairs; ++j) w[j] = base[e0 + (uint32_t)j];
+        for (int c = 0; c < kRunPairs / 2; ++c) {
+            const ulonglong2 v = base[c * nrun + rr];
+            w[2 * c] = v.x;
+            w[2 * c + 1] = v.y;
+        }
     };
     auto run = [&](const uint64_t (&w)[kRunPairs], bool ok, const double2 *ps, double *acc) {
         const double2 *row = ps + pair_row16(w[0]);
@@ -1711,8 +1728,7 @@ __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, con
             run(wc, (int64_t)kRunPairs * cl < p1 - p0, ps, acc);
         for (int r = cl + nl; (int64_t)kRunPairs * r < p1 - p0; r += nl) {   // items of more runs than consumer lanes
             uint64_t w[kRunPairs];
-#pragma unroll
-            for (int j = 0; j < kRunPairs; ++j) w[j] = P.pw[p0 + (uint32_t)(kRunPairs * r + j)];
+            load_run(w, p0, p1, r);
             run(w, true, ps, acc);
         }
         __syncthreads();
