@@ -59,9 +59,14 @@ typedef struct {
      * (Sec. 6, eq. sigInterp); default 20 (Sec. 5). */
     int32_t interp_order;
     /* Delay, in steps, between the newest ingested sample and the time at which
-     * wfp2d_evaluate reports u.  -1 (default) = ceil(p/2) - 1, which lets every
-     * interpolation stencil of the local part be centred.  0 = report u at the
-     * newest step with stencils clamped one-sided near zero delay. */
+     * wfp2d_evaluate reports u.  -1 (default) = ceil(p/2) - 1: every stencil of
+     * eq. sigInterp is the p grid samples nearest its node, which for delays
+     * below p/2 steps include samples newer than t_n, so u(t_n) is reported
+     * once they have arrived.  This departs from the paper's statement that
+     * only levels up to t_n are kept (Sec. 6); its accuracy is the paper's.
+     * 0 = report u(t_n) from past samples only, the stencils one-sided near zero
+     * delay: several orders less accurate (300 wavelengths, dt = 8/7150, p = 20:
+     * relative error 7e-6 .. 3.4e-5, against 1.6e-7 .. 2.6e-7 with the default). */
     int32_t lookahead;
     double Delta;     /* radial blending width of the truncated kernel (eq. TKdef); default 1 (Sec. 5) */
     double a;         /* near/far split margin, A+ = A + a (eq. Ap); 0 = rule max(1, delta + ln(1e15)/lambda_max) */
