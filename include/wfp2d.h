@@ -56,7 +56,7 @@ typedef struct {
      * WFP2D_PREC_FP64: everything in FP64. */
     int32_t precision;
     /* p, the order of the time interpolation of sigma in the local part
-     * (Sec. 6, eq. sigInterp); default 20 (Sec. 5). */
+     * (Sec. 6, eq. sigInterp); default 20 (Sec. 7). */
     int32_t interp_order;
     /* Delay, in steps, between the newest ingested sample and the time at which
      * wfp2d_evaluate reports u.  -1 (default) = ceil(p/2) - 1: every stencil of
@@ -162,7 +162,7 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
                         const wfp2d_opts *opts);
 
 /*
- * Advance one time step (Sec. 4.3, eqs. alphakEvolution, hggrid; Sec. 5,
+ * Advance one time step (Sec. 4.2, eqs. alphakEvolution, hggrid; Sec. 5,
  * eqs. betaEvolution, beta).  sigma: device pointer [M] float64,
  * sigma[j] = sigma_j(t_n) for the n-th call (n = 1, 2, ...), in the order of
  * src_xy.  Ingests the sample, then (once n > lookahead) runs the packed

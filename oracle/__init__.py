@@ -7,7 +7,7 @@ package imports nothing from it: the two share no code.
 Contents
 --------
 * :func:`u_direct` — the plain definition of the field (Sec. 1, eqs. solnRep,
-  Green; Sec. 5, eq. exactSol) by composite Gauss-Legendre quadrature with the
+  Green; Sec. 7, eq. exactSol) by composite Gauss-Legendre quadrature with the
   analytic signatures, FP64, OpenMP over (sample, source block), fixed-order
   compensated summation.  Optional windows give the local / near / far /
   history components of eq. split.

@@ -5,7 +5,7 @@
  * calls this file; only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark do.  It shares no code with the GPU path.
  *
- * What it computes (Sec. 1, eqs. solnRep, Green, pointSources; Sec. 5,
+ * What it computes (Sec. 1, eqs. solnRep, Green, pointSources; Sec. 7,
  * eq. exactSol):
  *
  *   u(x, t) = sum_j (1/2pi) int_{r_j}^{t} sigma_j(t - tau) / sqrt(tau^2 - r_j^2) dtau,

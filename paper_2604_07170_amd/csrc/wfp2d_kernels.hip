@@ -1,6 +1,6 @@
 // HIP kernels of the wfp2d per-step pipeline, written for gfx950 (wave64).
 //
-// Step (Sec. 4.3 and Sec. 5):   ingest sigma -> packed type-1 NUFFT of
+// Step (Sec. 4.2 and Sec. 5):   ingest sigma -> packed type-1 NUFFT of
 //   sigma(t_m) + i sigma(t_{m-LA}) (spread, row FFTs, column FFTs, Hermitian
 //   split into the near and lag rings) -> near-history recurrence per mode ->
 //   far-history SOE recurrence per far mode.
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_split(const typename cplx<R>::T *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Near history (Sec. 4.3).  With the trapezoid rule on the time grid,
+// Near history (Sec. 4.2).  With the trapezoid rule on the time grid,
 //   alpha(k, t_m) = dt sum_l sin(k l dt)/k w_l S(t_{m-l}),
 //   w_l = phi(l dt) phi(A+ - l dt)   (eq. alphak),
 // split into the blending edges (W-tap FIRs at delays 1..W-1 and

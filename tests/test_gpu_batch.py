@@ -3,7 +3,7 @@
 A captured step + evaluation replayed by one graph launch must reproduce the
 eagerly launched sequence; a batch of uneven instances advanced by one graph
 launch per step must match each instance run alone and the oracle (relative
-L2 <= 1e-6 per instance, the Sec. 5 accuracy at eps = 1e-7).
+L2 <= 1e-6 per instance, the Sec. 7 accuracy at eps = 1e-7).
 """
 import numpy as np
 import pytest

@@ -1,7 +1,7 @@
 """Parity of the HIP path with the oracle (GPU).
 
 End-to-end: relative L2 error over all sampled (target, step) pairs <= 1e-6,
-the accuracy the method targets at eps = 1e-7 (about six correct digits, Sec. 5).
+the accuracy the method targets at eps = 1e-7 (about six correct digits, Sec. 7).
 Stages: the type-1 NUFFT against the direct Fourier sum of eq. sighat, the
 near-history coefficients against eq. alphak evaluated by quadrature.
 """
@@ -214,12 +214,12 @@ def _curve_case(idx, precision, steps, n_near, n_any, seed):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_config5_circle_grid_targets(precision):
-    """Sec. 5.3: 10^5 sources on a circle that touches the edge of B, frequencies and onsets
+    """Sec. 7.3: 10^5 sources on a circle that touches the edge of B, frequencies and onsets
     rising along it, 900 x 900 target mesh; 8 targets x 2 steps after the far-history onset."""
     assert _curve_case(5, precision, [4400, 5000], n_near=6, n_any=2, seed=15) <= TOL_E2E
 
 
 def test_config6_wiggly_curve_grid_targets():
-    """Sec. 5.4: 10^6 sources on the oscillating curve, 900 x 900 target mesh; 2 targets x
+    """Sec. 7.4: 10^6 sources on the oscillating curve, 900 x 900 target mesh; 2 targets x
     2 steps after the far-history onset, in the benchmark's precision."""
     assert _curve_case(6, "mixed", [4400, 5000], n_near=1, n_any=1, seed=16) <= TOL_E2E

@@ -1,6 +1,6 @@
 """CPU pins of the library's host-side precomputation (no GPU needed).
 
-* derived parameters against the numbers printed in Sec. 5.2;
+* derived parameters against the numbers printed in Sec. 7.2;
 * the sum-of-exponentials rule of Sec. 2.3 against the closed form 1/sqrt(t^2-r^2);
 * the Hankel coefficients of eq. H against Table 1, and their kappa = 0 limit
   against a radial integral done independently with scipy;
@@ -32,13 +32,13 @@ def _read(name):
 
 
 def test_params_reproduce_sec52():
-    g = {r[0]: (float(r[1]), float(r[2])) for r in _read("params_sec52.txt")}
+    g = {r[0]: (float(r[1]), float(r[2])) for r in _read("params_sec72.txt")}
     P = pa.derive_params(g["dt"][0], int(g["W"][0]), g["tol"][0])
     assert P["K"] == pytest.approx(g["K"][0], abs=g["K"][1])
     assert P["dk"] == pytest.approx(g["dk"][0], abs=g["dk"][1])
     assert P["N"] == int(g["N"][0])
     assert P["delta"] == pytest.approx(g["delta"][0], abs=g["delta"][1])
-    # eq. dt holds with the paper's margin: K0 + 2b/delta <= K with K0 = 983 (Sec. 5.2)
+    # eq. dt holds with the paper's margin: K0 + 2b/delta <= K with K0 = 983 (Sec. 7.2)
     assert 983 + 2 * P["b"] / P["delta"] <= P["K"]
     # the lagged sample lies on the time grid: (A+ - delta)/dt is an integer
     assert (P["Aplus"] - P["delta"]) / g["dt"][0] == pytest.approx(P["LA"], abs=1e-6)

@@ -2,13 +2,13 @@
 the sums they stand for (CPU, numpy, with the library's own parameters, blend and
 sum-of-exponentials nodes).
 
-Near history (Sec. 4.3; eq. alphak discretised by the trapezoid rule on the time
+Near history (Sec. 4.2; eq. alphak discretised by the trapezoid rule on the time
 grid):
     alpha_n(kappa) = dt sum_{l=0}^{LA+W} w_l sin(kappa l dt)/kappa S_{n-l},
 with w_l = phi(l dt) on the opening edge l < W, 1 inside, and phi((LA+W-l) dt) on
 the closing edge LA < l <= LA+W.  The kernel holds the interior part l = W..LA as
 the pair D = sum sin(kappa l dt)/kappa S_{n-l}, C = sum cos(kappa l dt) S_{n-l},
-advanced by the exact rotation of the Lemma of Sec. 4.3 (one sample enters at
+advanced by the exact rotation of the Lemma of Sec. 4.2 (one sample enters at
 l = W-1, one leaves at l = LA), and adds both edges as (W-1)-tap FIRs
 (the structure of eq. hggrid).
 

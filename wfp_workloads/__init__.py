@@ -5,7 +5,7 @@ parameters of each source's time signature, and the time grid.  It holds none
 of the fast method's arithmetic and none of the reference evaluator's, so both
 the GPU path and the CPU oracle may draw their inputs from it.
 
-Signature families (Sec. 5, eq. exampleDensities, and the Gaussian-modulated
+Signature families (Sec. 7, eq. exampleDensities, and the Gaussian-modulated
 carrier used by the small configurations):
 
 * family 0 ("G"): sigma(t) = A exp(-(t-c)^2 / (2 s^2)) sin(w (t-c)) for t > t0,
@@ -187,7 +187,7 @@ def k0_family_g(omega_c: float, s: float, tol: float) -> float:
 
 
 def k0_family_e(omega_max: float, tol: float) -> float:
-    """eps-bandwidth of eq. exampleDensities: max|w| + 10 sqrt(log(1/eps)) (Sec. 5)."""
+    """eps-bandwidth of eq. exampleDensities: max|w| + 10 sqrt(log(1/eps)) (Sec. 7)."""
     return omega_max + 10.0 * math.sqrt(math.log(1.0 / tol))
 
 
@@ -201,7 +201,7 @@ def window_for(K0: float, dt: float, tol: float) -> int:
 
 
 def dt_for(K0: float, W: int, tol: float, margin: float = 0.9757) -> float:
-    """Time step from eq. dt with the margin used in Sec. 5.2 (8/7150 vs the bound)."""
+    """Time step from eq. dt with the margin used in Sec. 7.2 (8/7150 vs the bound)."""
     b = math.log(1.0 / tol)
     return margin * (math.pi - 2.0 * b / W) / K0
 
@@ -235,9 +235,9 @@ def family_e_workload(name, rng, src, L: float, nt: int, dt: float | None = None
     if dt is None:
         dt = dt_for(K0, W, tol)
     T = dt * nt if T_ref is None else T_ref
-    t0 = rng.uniform(1.5, 7.0, size=M) * (T / 8.0)     # Sec. 5.2 offsets, scaled to T
+    t0 = rng.uniform(1.5, 7.0, size=M) * (T / 8.0)     # Sec. 7.2 offsets, scaled to T
     z = rng.uniform(0.0, 1.0, size=M)
-    omega = omega_max * np.cbrt(z)                        # Sec. 5.2: 300 pi z^(1/3)
+    omega = omega_max * np.cbrt(z)                        # Sec. 7.2: 300 pi z^(1/3)
     return Workload(name=name, src=src, tgt=src.copy() if tgt is None else tgt,
                     family=np.full(M, FAMILY_E, np.int32), amp=np.ones(M), t0=t0,
                     omega=omega, s=np.zeros(M), dt=dt, nt=nt, W=W, tol=tol, p=p, K0=K0,
@@ -268,7 +268,7 @@ def config(idx: int, displaced_targets: bool = False) -> Workload:
         w = family_e_workload("cfg7_random_M1e6_grid900", rng, src, L=300.0, nt=7150, dt=8.0 / 7150.0, T_ref=8.0,
                               tgt=grid_targets(900))
     elif idx in (5, 6):
-        # the curve examples of Sec. 5: the Sec. 5.2 step, window and final time T = 8, a
+        # the curve examples of Sec. 7: the Sec. 7.2 step, window and final time T = 8, a
         # 900 x 900 target mesh (no target on a source), t0 rising from 1.5 to 7 along the
         # curve; on the circle omega rises linearly to 300 pi along it, on the wiggly curve
         # omega = 300 pi z^(1/3) with z uniform
@@ -292,7 +292,7 @@ def batch_instances(n: int = 64, nt: int = 1000, W: int = 16, tol: float = 1e-7,
                     m_range=(500, 20000), l_range=(10.0, 50.0)) -> list:
     """Independent scatterers of uneven size: star curves with M_i log-uniform in m_range
     and L_i ~ U(l_range) wavelengths across B, family E signatures, the time step of
-    eq. dt with the Sec. 5.2 margin for each instance's bandwidth."""
+    eq. dt with the Sec. 7.2 margin for each instance's bandwidth."""
     rng = np.random.default_rng(1003)
     L = rng.uniform(*l_range, size=n)
     M = np.floor(np.exp(rng.uniform(math.log(m_range[0]), math.log(m_range[1]), size=n))).astype(np.int64)
