@@ -697,44 +697,59 @@ __global__ __launch_bounds__(256) void k_far(const int32_t *__restrict__ far_pk,
 }
 
 // ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
 // Type-2 interpolation (eq. uhtraptrunc on the fine grid): u_h(x_i) = sum over
 // the w x w stencil of grid(origin_i + (a, b)) * wx_i[a] * wy_i[b].
-// Eight lanes serve one target: lane r sums the stencil rows r, r + 8 (a
-// contiguous run of w grid values each, read through the cache), and the
-// eight partial sums are reduced with lane shuffles.  Targets are taken in
-// tile order, so neighbouring targets read neighbouring grid lines, and the
-// blocks are remapped so that each XCD (workgroups are dealt to the 8 XCDs in
-// turn) takes one contiguous range of targets and their lines stay in its L2.
+// One workgroup per kTile x kTile tile of stencil origins: it stages the tile
+// and its w - 1 halo rows and columns of the grid in LDS with coalesced row
+// loads (each grid value is read from memory about (1 + (w - 1)/kTile)^2 times
+// in all), then each thread evaluates whole targets of the tile from LDS.
+// Tiles are remapped so that each XCD (workgroups are dealt to the 8 XCDs in
+// turn) takes one contiguous band of tiles, whose halos then meet in its L2.
 // Accumulation in FP64.
 // ---------------------------------------------------------------------------
-template <class R>
-__global__ __launch_bounds__(256) void k_interp(const R *__restrict__ cgrid, const int2 *__restrict__ base, const R *__restrict__ wts,
-                                                const int32_t *__restrict__ tlist, double *__restrict__ uh, int w, int Lpad,
-                                                int64_t Nx)
+constexpr int kInterpThreads = 128;
+template <class R, int WM>   // kernel width w <= WM: the target's weights are held in registers
+__global__ __launch_bounds__(kInterpThreads) void k_interp(const R *__restrict__ cgrid, const int2 *__restrict__ base,
+                                                           const R *__restrict__ wts, const int32_t *__restrict__ tlist,
+                                                           const int32_t *__restrict__ toff, double *__restrict__ uh, int w,
+                                                           int Lpad, int ntx)
 {
-    const int per_xcd = (int)(gridDim.x >> 3);      // the grid is a multiple of 8 blocks
-    const int lb = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
-    const int64_t gid = (int64_t)lb * blockDim.x + threadIdx.x;
-    const int64_t e = gid >> 3;
-    const int r = (int)(gid & 7);
-    double part = 0.0;
-    int i = 0;
-    if (e < Nx) {
-        i = tlist[e];                                 // output slot (sorted target order)
+    extern __shared__ unsigned char interp_lds[];
+    R *const tl = reinterpret_cast<R *>(interp_lds);   // [S][S + 1], S = kTile + w - 1
+    const int ntile = ntx * ntx, per_xcd = (ntile + 7) >> 3;
+    const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= ntile) return;
+    const int e0 = toff[tile], e1 = toff[tile + 1];
+    if (e0 == e1) return;
+    const int ox = (tile % ntx) * kTile, oy = (tile / ntx) * kTile, S = kTile + w - 1, ld = S + 1;
+    for (int q = threadIdx.x; q < S * S; q += kInterpThreads) {
+        const int yy = q / S, xx = q - yy * S, gx = ox + xx, gy = oy + yy;
+        tl[yy * ld + xx] = (gx < Lpad && gy < Lpad) ? cgrid[(size_t)gy * Lpad + gx] : R(0);
+    }
+    __syncthreads();
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kInterpThreads) {
         const int2 b = base[e];                       // origins and weights are stored in processing order
         const R *__restrict__ wi = wts + (size_t)e * 2 * w;
-        for (int bb = r; bb < w; bb += 8) {
-            const R *__restrict__ row = cgrid + (size_t)(b.y + bb) * Lpad + b.x;
-            double s = 0.0;
-            for (int a = 0; a < w; ++a) s += (double)wi[a] * (double)row[a];
-            part += s * (double)wi[w + bb];
+        double wx[WM], wy[WM];
+#pragma unroll
+        for (int a = 0; a < WM; ++a) {
+            wx[a] = a < w ? (double)wi[a] : 0.0;
+            wy[a] = a < w ? (double)wi[w + a] : 0.0;
         }
+        const R *row = tl + (b.y - oy) * ld + (b.x - ox);
+        double acc = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < WM; ++bb) {
+            if (bb < w) {
+                double sx = 0.0;
+#pragma unroll
+                for (int a = 0; a < WM; ++a)
+                    if (a < w) sx = fma(wx[a], (double)row[bb * ld + a], sx);
+                acc = fma(sx, wy[bb], acc);
+            }
+        }
+        uh[tlist[e]] = acc;
     }
-    part += __shfl_xor(part, 4, 8);
-    part += __shfl_xor(part, 2, 8);
-    part += __shfl_xor(part, 1, 8);
-    if (e < Nx && r == 0) uh[i] = part;
 }
 
 // ---------------------------------------------------------------------------
@@ -1996,16 +2011,29 @@ hipError_t launch_fft_rows2(Plan &p)
     return hipGetLastError();
 }
 
-hipError_t launch_interp(Plan &p)
+template <class R, int WM>
+static void interp_as(Plan &p)
 {
     const Geom &g = p.g;
-    const unsigned nb = (unsigned)(((p.Nx * 8 + 255) / 256 + 7) / 8 * 8);   // padded to a multiple of 8 (XCD remap)
-    if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL(k_interp<float>, dim3(nb), dim3(256), 0, p.stream, (const float *)p.d_cgrid, p.d_tgt_base,
-                           (const float *)p.d_tgt_wts, p.d_ttile_tgt, p.d_uh, g.w, g.Lpad, p.Nx);
-    else
-        hipLaunchKernelGGL(k_interp<double>, dim3(nb), dim3(256), 0, p.stream, (const double *)p.d_cgrid, p.d_tgt_base,
-                           (const double *)p.d_tgt_wts, p.d_ttile_tgt, p.d_uh, g.w, g.Lpad, p.Nx);
+    const int ntile = g.ntx * g.ntx, S = kTile + g.w - 1;
+    const unsigned nb = (unsigned)((ntile + 7) / 8 * 8);   // padded to a multiple of 8 (XCD remap)
+    hipLaunchKernelGGL((k_interp<R, WM>), dim3(nb), dim3(kInterpThreads), (size_t)S * (S + 1) * sizeof(R), p.stream,
+                       (const R *)p.d_cgrid, p.d_tgt_base, (const R *)p.d_tgt_wts, p.d_ttile_tgt, p.d_ttile_off, p.d_uh, g.w,
+                       g.Lpad, g.ntx);
+}
+
+template <class R>
+static void interp_typed(Plan &p)
+{
+    if (p.g.w <= 8) interp_as<R, 8>(p);
+    else if (p.g.w <= 12) interp_as<R, 12>(p);
+    else interp_as<R, 16>(p);
+}
+
+hipError_t launch_interp(Plan &p)
+{
+    if (p.precision == WFP2D_PREC_MIXED) interp_typed<float>(p);
+    else interp_typed<double>(p);
     return hipGetLastError();
 }
 
