@@ -130,7 +130,7 @@ def stage_kernel(stage: str, info: dict):
     if stage == "local":
         path = info["local_path"]
         if path == 2:
-            return "k_local_pairs", (info["n_levels"], info["cheb_degree"])
+            return "k_local_pc", (info["n_levels"], info["cheb_degree"])
         return ("k_local_fast", (info["n_levels"],)) if path == 1 else ("k_local", ())
     return table[stage]
 

@@ -677,6 +677,17 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
             }
         p.d_cpow = p.alloc<double>((int64_t)cpow.size());
         upload(p.d_cpow, cpow);
+        // the producer may skip MFMA k-steps below a row block's first panel when every
+        // regular panel k has exactly zero coefficients on the levels d < k
+        bool zero_below = true;
+        for (int sp = 0; sp < p.n_reg && zero_below; ++sp)
+            for (int d = 0; d < std::min(sp, nl) && zero_below; ++d)
+                for (int c = 0; c < D; ++c)
+                    if (cpow[((size_t)sp * kChebDeg + c) * nl + d] != 0.0) {
+                        zero_below = false;
+                        break;
+                    }
+        p.pc_skip = zero_below ? 1 : 0;
     }
     // local-pair count (reported; without pair lists the local kernel finds pairs through the cell lists)
     if (!p.local_pairs) {

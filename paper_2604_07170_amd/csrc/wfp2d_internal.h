@@ -221,6 +221,7 @@ struct Plan {
     uint32_t *d_pair_dent = nullptr;
     int32_t *d_pair_dtg = nullptr, *d_pair_dsg = nullptr;   // pairs with r < dt/2: sorted target, source
     int64_t pair_ndy = 0;
+    int32_t pc_skip = 0;              //   the regular panels' table is zero below each panel's level (MFMA k-steps skipped)
     void *d_pc_desc = nullptr;        // producer / consumer kernel: item descriptors (32 bytes each)
     int32_t *d_pc_ioff = nullptr;     //   first item of each workgroup
     int32_t pc_grid = 0;              //   workgroups (one per CU); 0 = kernel not used

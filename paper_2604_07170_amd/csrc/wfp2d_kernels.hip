@@ -1546,7 +1546,7 @@ constexpr int kDescWords = 8;
 // (RB == 2), in LDS (RB == 4: the table is staged once per launch), or read from cache (RB == 3).
 template <int NL, int NTERM, int RB>
 __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g, int nprod,
-                                                   int nbmax)
+                                                   int skip)
 {
     // Every global load is issued at least one item before its value is used, and the loop
     // bodies have no data-dependent branches around loads or MFMAs, so the in-order wait on
@@ -1611,12 +1611,24 @@ __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, con
             mfma_d4 acc[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) acc[r] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+            if (kLdsA && skip) {
+                // A regular panel k weights only levels d >= k (its nodes lie at delays >= k dt and
+                // the centred stencils reach back, never forward, from there; the plan checks the
+                // table): block r holds panels >= (64 r)/D, so its k-steps below kst(r) are zero.
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
+                for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(kRegA ? ca[kRegA ? r : 0][ks] : a_op(r, ks), bv[ks], acc[r],
-                                                                  0, 0, 0);
+                    for (int r = 0; r < RB; ++r)
+                        if (ks >= (64 * r / D) / 4)
+                            acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_op(r, ks), bv[ks], acc[r], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(kRegA ? ca[kRegA ? r : 0][ks] : a_op(r, ks), bv[ks], acc[r],
+                                                                      0, 0, 0);
+            }
             // D[lane][e] = C[row = (wave + r nprod) 16 + lane / 16 + 4 e][q = lane % 16]; with nprod
             // known at compile time the stores share one address register and immediate offsets
             double *const dq = dst + (lane & 15) * psiSrc + wave * 16 + (lane >> 4);
@@ -2121,12 +2133,12 @@ hipError_t launch_local(Plan &p)
         int rb = 2;
         const int nprod = pc_producers(p.n_reg, p.local_terms, &rb, p.g.nlev);
         const unsigned grid = (unsigned)p.pc_grid;
-        const int nbmax = 0;
+        const int skip = p.pc_skip;
         const size_t lds = (size_t)2 * kFastSrc * (p.n_reg * p.local_terms + 2) * sizeof(double) +
                            (rb == 4 ? (size_t)kPcLdsRows * 4 * ((p.g.nlev + 3) / 4) * sizeof(double) : 0);
         const PairLists P = pair_lists(p);
 #define WFP2D_LAUNCH_PC(NLV, NTV, RBV) \
-    hipLaunchKernelGGL((k_local_pc<NLV, NTV, RBV>), dim3(grid), dim3(1024), lds, p.stream, A, P, p.d_step, p.g, nprod, nbmax)
+    hipLaunchKernelGGL((k_local_pc<NLV, NTV, RBV>), dim3(grid), dim3(1024), lds, p.stream, A, P, p.d_step, p.g, nprod, skip)
 #define WFP2D_LAUNCH_PC_NL(NTV, RBV) \
     do { if (p.g.nlev == 35) WFP2D_LAUNCH_PC(35, NTV, RBV); else WFP2D_LAUNCH_PC(43, NTV, RBV); } while (0)
         if (rb == 4 && p.local_terms == 16) WFP2D_LAUNCH_PC(35, 16, 4);

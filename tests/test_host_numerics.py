@@ -232,3 +232,24 @@ def test_power_basis_with_every_term_matches_the_chebyshev_table():
     power = pa.host_eval(10, [dt, W, p, -1, tol, 20] + list(r), len(r) * nl).reshape(len(r), nl)
     cheb = pa.host_eval(5, [dt, W, p, -1, tol] + list(r), len(r) * nl).reshape(len(r), nl)
     assert np.abs(power - cheb).max() <= 1e-12 * np.abs(cheb).max()
+
+
+def test_regular_panel_weights_vanish_below_its_level():
+    """A pair in regular panel k (k dt <= r < (k + 1) dt) weights only sigma levels d >= k:
+    its quadrature nodes lie at delays >= r and each centred p-point stencil reaches no
+    further forward than the node's own step (Sec. 6, eqs. ul_GL, sigInterp).  The pair
+    kernel's producer skips the MFMA k-steps of those levels, so the zeros must be exact
+    in the power-basis table it uses (the plan checks the same on its table)."""
+    import paper_2604_07170_amd as pa
+    dt, W, p, tol = 8.0 / 7150.0, 16, 20, 1e-7
+    nl = 35
+    r = []
+    for k in range(W):
+        lo = max(k, 0.5) * dt
+        r += list(np.linspace(lo, (k + 1) * dt, 6, endpoint=False)[1:])
+    for terms in (16, 20):
+        eta = pa.host_eval(10, [dt, W, p, -1, tol, terms] + r, len(r) * nl).reshape(len(r), nl)
+        for i, ri in enumerate(r):
+            k = int(ri / dt)
+            assert np.all(eta[i, :k] == 0.0), (terms, k)
+            assert np.any(eta[i, k:] != 0.0)
