@@ -276,6 +276,32 @@ wfp2d_status wfp2d_save_state(wfp2d_plan plan, void *dst, int64_t bytes);
 wfp2d_status wfp2d_load_state(wfp2d_plan plan, const void *src, int64_t bytes);
 
 /*
+ * Spectral checkpoints: the same state without the sigma history ring (the
+ * Fourier rings, the near-history state, alpha_tot, the SOE state and the step
+ * count; at 10^6 sources 4.5 GB instead of 39 GB), in a caller-owned device
+ * buffer of at least wfp2d_spectral_state_bytes bytes.  The history ring holds
+ * samples the caller already has (the lagged transform of eq. sighat and the
+ * local part's levels of eq. sigInterp reach back sigma_depth steps), so after
+ * wfp2d_load_spectral_state, which zeroes the ring and sets the step count to
+ * the blob's n, the caller puts back sigma(t_l) for every l with
+ * max(1, n - sigma_depth + 1) <= l <= n with wfp2d_put_sigma before the next
+ * wfp2d_step or wfp2d_evaluate.  A spectral blob is not a full blob: each load
+ * accepts only its own kind.  Errors: as wfp2d_save_state / wfp2d_load_state.
+ */
+wfp2d_status wfp2d_spectral_state_bytes(wfp2d_plan plan, int64_t *bytes);
+wfp2d_status wfp2d_save_spectral_state(wfp2d_plan plan, void *dst, int64_t bytes);
+wfp2d_status wfp2d_load_spectral_state(wfp2d_plan plan, const void *src, int64_t bytes);
+
+/*
+ * Store sigma(t_l) (layout, pointer kind and non-finite check as wfp2d_step)
+ * in the history ring as step l's sample, without advancing the plan; for
+ * refilling the ring after wfp2d_load_spectral_state.  l must be a step the
+ * ring still holds: 1 <= l <= n and l > n - sigma_depth (n = steps so far).
+ * Errors: ERR_ARG (NULL sigma, l out of reach), ERR_STATE, ERR_DEVICE.
+ */
+wfp2d_status wfp2d_put_sigma(wfp2d_plan plan, int64_t l, const double *sigma);
+
+/*
  * Graph replay of one plan.  wfp2d_graph_capture records one step followed by
  * one evaluation into a HIP graph, reading the samples from the fixed device
  * pointer sigma [M] and writing u into the fixed device pointer u [Nx]

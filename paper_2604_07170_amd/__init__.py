@@ -95,6 +95,10 @@ def load_library():
     lib.wfp2d_reset.argtypes = [vp]
     lib.wfp2d_save_state.argtypes = [vp, vp, i64]
     lib.wfp2d_load_state.argtypes = [vp, vp, i64]
+    lib.wfp2d_spectral_state_bytes.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.wfp2d_save_spectral_state.argtypes = [vp, vp, i64]
+    lib.wfp2d_load_spectral_state.argtypes = [vp, vp, i64]
+    lib.wfp2d_put_sigma.argtypes = [vp, i64, vp]
     lib.wfp2d_set_spread_tile.argtypes = [vp, i32]
     lib.wfp2d_time_spread.argtypes = [vp, i32, i32, dp]
     for f in ("wfp2d_default_opts", "wfp2d_init", "wfp2d_step", "wfp2d_evaluate", "wfp2d_query", "wfp2d_destroy",
@@ -102,7 +106,8 @@ def load_library():
               "wfp2d_graph_launch", "wfp2d_batch_create", "wfp2d_batch_launch", "wfp2d_batch_destroy",
               "wfp2d_set_spread_tile", "wfp2d_time_spread", "wfp2d_evaluate_dot", "wfp2d_adjoint_init",
               "wfp2d_state_bytes", "wfp2d_save_state", "wfp2d_load_state", "wfp2d_reset",
-              "wfp2d_evaluate_noalloc"):
+              "wfp2d_evaluate_noalloc", "wfp2d_spectral_state_bytes", "wfp2d_save_spectral_state",
+              "wfp2d_load_spectral_state", "wfp2d_put_sigma"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -289,6 +294,44 @@ class Wfp2d:
         if not (buf.is_cuda and buf.dtype == t.uint8 and buf.is_contiguous()):
             raise ValueError("state buffer must be a contiguous uint8 CUDA tensor")
         self._check(self.lib.wfp2d_load_state(self.h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
+
+    def spectral_state_bytes(self) -> int:
+        n = ctypes.c_int64(0)
+        self._check(self.lib.wfp2d_spectral_state_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def save_spectral_state(self, buf=None):
+        """Copy the state without the sigma history ring into a uint8 CUDA tensor."""
+        t = self._torch
+        n = self.spectral_state_bytes()
+        if buf is None:
+            buf = t.empty(n, dtype=t.uint8, device=self.device)
+        if not (buf.is_cuda and buf.dtype == t.uint8 and buf.numel() >= n and buf.is_contiguous()):
+            raise ValueError("state buffer must be a contiguous uint8 CUDA tensor of spectral_state_bytes() bytes")
+        self._check(self.lib.wfp2d_save_spectral_state(self.h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
+        return buf
+
+    def load_spectral_state(self, buf):
+        """Restore a spectral checkpoint; then put_sigma(l, ...) for the ring's steps
+        max(1, n - sigma_depth + 1)..n (n = info()["steps_ingested"])."""
+        t = self._torch
+        if not (buf.is_cuda and buf.dtype == t.uint8 and buf.is_contiguous()):
+            raise ValueError("state buffer must be a contiguous uint8 CUDA tensor")
+        self._check(self.lib.wfp2d_load_spectral_state(self.h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
+
+    def put_sigma(self, l: int, sigma):
+        t = self._torch
+        if self.host_pointers:
+            a = np.ascontiguousarray(sigma, np.float64)
+            if a.size != self.M:
+                raise ValueError("sigma must hold M float64 values")
+            self._check(self.lib.wfp2d_put_sigma(self.h, int(l), a.ctypes.data_as(ctypes.c_void_p)))
+            return
+        if not (isinstance(sigma, t.Tensor) and sigma.is_cuda and sigma.dtype == t.float64 and sigma.numel() == self.M):
+            raise ValueError("sigma must be a float64 CUDA tensor with M elements")
+        sigma = sigma.contiguous()
+        self._keep = [sigma]
+        self._check(self.lib.wfp2d_put_sigma(self.h, int(l), ctypes.c_void_p(sigma.data_ptr())))
 
     # -- spreading tile shape (autotuned by paper_2604_07170_amd.autotune) --
     SPREAD_TILES = {1: (8, 8), 2: (16, 8), 3: (16, 16), 4: (32, 16), 5: (32, 32)}

@@ -1076,28 +1076,76 @@ struct StateHeader {
 constexpr uint64_t kStateMagic = 0x7766703264737461ull;   // "wfp2dsta"
 }  // namespace
 
-static size_t state_layout(const Plan &p, std::vector<size_t> *offs)
+// The buffers a checkpoint holds: all of the evolving state, or (spectral) all but the sigma
+// history ring, which the caller then refills with wfp2d_put_sigma.
+static std::vector<std::pair<void *, size_t>> state_buffers(const Plan &p, bool spectral)
+{
+    std::vector<std::pair<void *, size_t>> v;
+    for (const auto &b : p.state_bufs)
+        if (!(spectral && b.first == (void *)p.d_sig)) v.push_back(b);
+    return v;
+}
+
+static size_t state_layout(const Plan &p, std::vector<size_t> *offs, bool spectral = false)
 {
     size_t off = 256;
-    for (const auto &b : p.state_bufs) {
+    for (const auto &b : state_buffers(p, spectral)) {
         if (offs) offs->push_back(off);
         off += (b.second + 255) / 256 * 256;
     }
     return off;
 }
 
-static StateHeader state_header(const Plan &p)
+static StateHeader state_header(const Plan &p, bool spectral = false)
 {
     StateHeader h{};
     h.magic = kStateMagic;
-    h.version = 1;
+    h.version = spectral ? 2 : 1;
     h.steps = (uint64_t)p.steps;
     h.M = (uint64_t)p.M;
     h.Nx = (uint64_t)p.Nx;
     h.n_modes = (uint64_t)p.n_modes;
-    h.n_bufs = p.state_bufs.size();
-    h.bytes = state_layout(p, nullptr);
+    h.n_bufs = state_buffers(p, spectral).size();
+    h.bytes = state_layout(p, nullptr, spectral);
     return h;
+}
+
+static void save_state(Plan &p, void *dst, int64_t bytes, bool spectral)
+{
+    std::vector<size_t> offs;
+    const size_t need = state_layout(p, &offs, spectral);
+    if (!dst || bytes < (int64_t)need) fail(WFP2D_ERR_ARG, "state buffer NULL or smaller than the state's size");
+    hip_check(hipSetDevice(p.device), "hipSetDevice");
+    const StateHeader h = state_header(p, spectral);
+    hip_check(hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyHostToDevice, p.stream), "state header");
+    const auto bufs = state_buffers(p, spectral);
+    for (size_t k = 0; k < bufs.size(); ++k)
+        hip_check(hipMemcpyAsync((char *)dst + offs[k], bufs[k].first, bufs[k].second, hipMemcpyDeviceToDevice, p.stream),
+                  "state copy");
+    hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+}
+
+static void load_state(Plan &p, const void *src, int64_t bytes, bool spectral)
+{
+    std::vector<size_t> offs;
+    const size_t need = state_layout(p, &offs, spectral);
+    if (!src || bytes < (int64_t)need) fail(WFP2D_ERR_ARG, "state buffer NULL or smaller than the state's size");
+    hip_check(hipSetDevice(p.device), "hipSetDevice");
+    hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+    StateHeader h{};
+    hip_check(hipMemcpy(&h, src, sizeof h, hipMemcpyDeviceToHost), "state header");
+    const StateHeader mine = state_header(p, spectral);
+    if (h.magic != kStateMagic || h.version != mine.version || h.M != mine.M || h.Nx != mine.Nx ||
+        h.n_modes != mine.n_modes || h.n_bufs != mine.n_bufs || h.bytes != mine.bytes)
+        fail(WFP2D_ERR_ARG, "state blob does not belong to a plan of this geometry and kind");
+    const auto bufs = state_buffers(p, spectral);
+    for (size_t k = 0; k < bufs.size(); ++k)
+        hip_check(hipMemcpyAsync(bufs[k].first, (const char *)src + offs[k], bufs[k].second, hipMemcpyDeviceToDevice, p.stream),
+                  "state copy");
+    if (spectral)   // levels at or before step 0 are zero; the caller puts back the others
+        hip_check(launch_zero_f64(p, p.d_sig, p.g.sig_depth * p.M), "sigma ring reset");
+    hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+    p.steps = (int64_t)h.steps;
 }
 
 wfp2d_status wfp2d_reset(wfp2d_plan plan)
@@ -1125,43 +1173,49 @@ wfp2d_status wfp2d_state_bytes(wfp2d_plan plan, int64_t *bytes)
 wfp2d_status wfp2d_save_state(wfp2d_plan plan, void *dst, int64_t bytes)
 {
     if (!plan) return WFP2D_ERR_STATE;
-    WFP2D_GUARD(plan, {
-        Plan &p = plan->p;
-        std::vector<size_t> offs;
-        const size_t need = state_layout(p, &offs);
-        if (!dst || bytes < (int64_t)need) fail(WFP2D_ERR_ARG, "state buffer NULL or smaller than wfp2d_state_bytes");
-        hip_check(hipSetDevice(p.device), "hipSetDevice");
-        const StateHeader h = state_header(p);
-        hip_check(hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyHostToDevice, p.stream), "state header");
-        for (size_t k = 0; k < p.state_bufs.size(); ++k)
-            hip_check(hipMemcpyAsync((char *)dst + offs[k], p.state_bufs[k].first, p.state_bufs[k].second,
-                                     hipMemcpyDeviceToDevice, p.stream), "state copy");
-        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
-    });
+    WFP2D_GUARD(plan, { save_state(plan->p, dst, bytes, false); });
     return WFP2D_OK;
 }
 
 wfp2d_status wfp2d_load_state(wfp2d_plan plan, const void *src, int64_t bytes)
 {
     if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, { load_state(plan->p, src, bytes, false); });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_spectral_state_bytes(wfp2d_plan plan, int64_t *bytes)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    if (!bytes) return WFP2D_ERR_ARG;
+    *bytes = (int64_t)state_layout(plan->p, nullptr, true);
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_save_spectral_state(wfp2d_plan plan, void *dst, int64_t bytes)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, { save_state(plan->p, dst, bytes, true); });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_load_spectral_state(wfp2d_plan plan, const void *src, int64_t bytes)
+{
+    if (!plan) return WFP2D_ERR_STATE;
+    WFP2D_GUARD(plan, { load_state(plan->p, src, bytes, true); });
+    return WFP2D_OK;
+}
+
+wfp2d_status wfp2d_put_sigma(wfp2d_plan plan, int64_t n, const double *sigma)
+{
+    if (!plan) return WFP2D_ERR_STATE;
     WFP2D_GUARD(plan, {
         Plan &p = plan->p;
-        std::vector<size_t> offs;
-        const size_t need = state_layout(p, &offs);
-        if (!src || bytes < (int64_t)need) fail(WFP2D_ERR_ARG, "state buffer NULL or smaller than wfp2d_state_bytes");
+        if (!sigma) fail(WFP2D_ERR_ARG, "NULL sigma");
+        if (n < 1 || n > p.steps || n <= p.steps - p.g.sig_depth)
+            fail(WFP2D_ERR_ARG, "step outside the sigma ring's reach (steps - depth < n <= steps, n >= 1)");
         hip_check(hipSetDevice(p.device), "hipSetDevice");
-        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
-        StateHeader h{};
-        hip_check(hipMemcpy(&h, src, sizeof h, hipMemcpyDeviceToHost), "state header");
-        const StateHeader mine = state_header(p);
-        if (h.magic != kStateMagic || h.version != mine.version || h.M != mine.M || h.Nx != mine.Nx ||
-            h.n_modes != mine.n_modes || h.n_bufs != mine.n_bufs || h.bytes != mine.bytes)
-            fail(WFP2D_ERR_ARG, "state blob does not belong to a plan of this geometry");
-        for (size_t k = 0; k < p.state_bufs.size(); ++k)
-            hip_check(hipMemcpyAsync(p.state_bufs[k].first, (const char *)src + offs[k], p.state_bufs[k].second,
-                                     hipMemcpyDeviceToDevice, p.stream), "state copy");
-        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
-        p.steps = (int64_t)h.steps;
+        hip_check(launch_ingest_at(p, stage_sigma(p, sigma), n), "put sigma");
     });
     return WFP2D_OK;
 }

@@ -87,6 +87,7 @@ struct Plan;
 // ---- launchers (kernels file) ----
 hipError_t launch_step_begin(Plan &p);
 hipError_t launch_ingest(Plan &p, const double *sigma_in);   // tests samples when p.d_nonfinite is set
+hipError_t launch_ingest_at(Plan &p, const double *sigma_in, int64_t n);   // sigma(t_n) into its ring slot, likewise
 hipError_t launch_spread(Plan &p);
 hipError_t kernel_setup(Plan &p);
 hipError_t fft_setup(Plan &p);

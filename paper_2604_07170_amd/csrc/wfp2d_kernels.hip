@@ -62,6 +62,20 @@ __global__ void k_ingest(const double *__restrict__ in, const int32_t *__restric
     sig[pmod(step[0], depth) * M + j] = v;
 }
 
+// sigma(t_n) of a past step n into its ring slot (checkpoint restore), as k_ingest stores it
+__global__ void k_ingest_slot(const double *__restrict__ in, const int32_t *__restrict__ perm, double *__restrict__ sig,
+                              int64_t M, int64_t slot, unsigned long long *__restrict__ nonfinite)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    double v = in[perm[j]];
+    if (nonfinite && !isfinite(v)) {
+        v = 0.0;
+        atomicAdd(nonfinite, 1ull);
+    }
+    sig[slot * M + j] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Type-1 spreading of c_j = sigma_cur[j] + i sigma_lag[j] onto the band grid.
 // One wave owns one TX x TY tile of the grid and a precomputed list of the
@@ -1831,6 +1845,14 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 hipError_t launch_step_begin(Plan &p)
 {
     hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, p.stream, p.d_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_ingest_at(Plan &p, const double *sigma_in, int64_t n)
+{
+    const int64_t slot = ((n % p.g.sig_depth) + p.g.sig_depth) % p.g.sig_depth;
+    hipLaunchKernelGGL(k_ingest_slot, dim3(nblk(p.M, 256)), dim3(256), 0, p.stream, sigma_in, p.d_src_perm, p.d_sig, p.M, slot,
+                       p.d_nonfinite);
     return hipGetLastError();
 }
 

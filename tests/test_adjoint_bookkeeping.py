@@ -26,7 +26,8 @@ class KernelPlan:
         self.reset()
 
     def info(self):
-        return {"lookahead": self.L}
+        # samples older than the kernel's span are never read again: the ring's depth
+        return {"lookahead": self.L, "sigma_depth": self.kern.shape[0]}
 
     def reset(self):
         self.hist = []
@@ -66,6 +67,19 @@ class KernelPlan:
 
     def load_state(self, st):
         self.hist = [h.clone() for h in st]
+
+    # spectral checkpoint: everything but the sample history, here just the step count; the
+    # samples come back through put_sigma, and any the caller does not put back stay zero
+    def save_spectral_state(self):
+        return len(self.hist)
+
+    def load_spectral_state(self, n):
+        self.hist = [torch.zeros(self.M, dtype=torch.float64) for _ in range(n)]
+
+    def put_sigma(self, l, sigma):
+        n = len(self.hist)
+        assert 1 <= l <= n and l > n - self.info()["sigma_depth"]
+        self.hist[l - 1] = sigma.detach().double().clone()
 
     def close(self):
         pass
@@ -114,8 +128,11 @@ def test_strength_gradient_is_the_transpose():
     assert np.allclose(Ar.grad.numpy(), ref, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("spectral", [False, True])
 @pytest.mark.parametrize("every", [1, 3, 5, 100])
-def test_checkpointed_loss_equals_stored(every):
+def test_checkpointed_loss_equals_stored(every, spectral):
+    """Also with spectral checkpoints, whose restore puts back exactly the samples the
+    history still reads (the stand-in zeroes the rest, so a short refill shows)."""
     kern, S, plan, run, A, L, nt, m0 = _setup(seed=2, nt=13, m0=3)
     Y = torch.as_tensor(np.random.default_rng(6).standard_normal((nt - m0 + 1, run.Nx)))
 
@@ -128,7 +145,7 @@ def test_checkpointed_loss_equals_stored(every):
     L1 = (0.5 * w[:, None] * (u - Y) ** 2).sum()
     L1.backward()
     A2 = A.clone().requires_grad_(True)
-    L2 = strength_loss_checkpointed(A2, run, loss_fn, every=every)
+    L2 = strength_loss_checkpointed(A2, run, loss_fn, every=every, spectral=spectral)
     L2.backward()
     l1, l2 = float(L1.detach()), float(L2.detach())
     assert abs(l1 - l2) <= 1e-12 * abs(l1)

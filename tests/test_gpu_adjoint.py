@@ -163,7 +163,8 @@ def test_gradient_against_oracle_transpose(precision):
     assert err <= 1e-6
 
 
-def test_checkpointed_loss_matches_stored_field():
+@pytest.mark.parametrize("spectral", [False, True])
+def test_checkpointed_loss_matches_stored_field(spectral):
     import torch
     from paper_2604_07170_amd.adjoint import StrengthRun, strength_field, strength_loss_checkpointed
     from wfp_workloads import config
@@ -185,14 +186,93 @@ def test_checkpointed_loss_matches_stored_field():
     L1 = (0.5 * wts[:, None] * (u - Y) ** 2).sum()
     L1.backward()
     A2 = torch.as_tensor(w.amp, dtype=torch.float64, device=dev).requires_grad_(True)
-    L2 = strength_loss_checkpointed(A2, run, loss_fn, every=17)
+    L2 = strength_loss_checkpointed(A2, run, loss_fn, every=17, spectral=spectral)
     L2.backward()
     dl = abs(float(L1) - float(L2)) / abs(float(L1))
     dg = rel_l2(A2.grad.cpu().numpy(), A1.grad.cpu().numpy())
-    print(f"checkpointed vs stored: loss rel {dl:.1e}, grad rel {dg:.1e}")
+    print(f"checkpointed (spectral {spectral}, sigma ring of {plan.info()['sigma_depth']} steps) vs stored: "
+          f"loss rel {dl:.1e}, grad rel {dg:.1e}")
     run.close()
     plan.close()
     assert dl <= 1e-12 and dg <= 1e-12
+
+
+def test_fd_32_strengths_config4_spectral_checkpoints():
+    """The 10^6-source, 300-wavelength geometry (sources = targets, dt = 8/7150), FP64, with
+    the signature onsets moved into the first steps so that a short window carries signal:
+    the gradient of loss = 1/2 sum_m |u(t_m)|^2 over m = 21..40 through spectral checkpoints
+    every 8 steps (the Fourier history without the sigma ring, refilled from the signatures
+    on restore) against central differences on 32 seeded strengths (exact for this
+    quadratic loss up to rounding)."""
+    import dataclasses
+    import torch
+    import paper_2604_07170_amd as pa
+    from paper_2604_07170_amd.adjoint import StrengthRun, strength_field, strength_loss_checkpointed
+    from wfp_workloads import config
+    dev = torch.device("cuda", 0)
+    w = config(4)
+    w = dataclasses.replace(w, t0=np.random.default_rng(21).uniform(0.0, 0.02, size=w.M))
+    nt, m0 = 40, 21
+    plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision="fp64", interp_order=w.p)
+    la = plan.info()["lookahead"]
+    full, spec = plan.state_bytes(), plan.spectral_state_bytes()
+    print(f"state blob {full / 2**30:.1f} GiB, spectral {spec / 2**30:.1f} GiB")
+    assert spec < 0.25 * full
+    wu = dataclasses.replace(w, amp=np.ones(w.M))
+    params = wu.torch_params(dev)
+    S = torch.stack([wu.sigma_torch(l * w.dt, dev, params) for l in range(1, nt + la + 1)])
+    run = StrengthRun(plan, lambda l: S[l - 1], nt=nt, m0=m0)
+
+    def loss_fn(m, um):
+        return 0.5 * (um * um).sum()
+
+    A0 = torch.as_tensor(w.amp, dtype=torch.float64, device=dev)
+    A = A0.clone().requires_grad_(True)
+    L = strength_loss_checkpointed(A, run, loss_fn, every=8)
+    L.backward()
+    grad = A.grad.detach().cpu().numpy()
+    idx = np.sort(np.random.default_rng(32).choice(w.M, size=32, replace=False))
+    h = 1.0
+    fd = np.zeros(len(idx))
+    for k, j in enumerate(idx):
+        e = torch.zeros_like(A0)
+        e[j] = h
+        up = strength_field(A0 + e, run)
+        um = strength_field(A0 - e, run)
+        fd[k] = float(0.5 * ((up * up).sum() - (um * um).sum())) / (2 * h)
+    err = rel_l2(grad[idx], fd)
+    print(f"config 4 geometry, FP64, spectral checkpoints: adjoint vs central differences {err:.2e} "
+          f"over 32 strengths (|fd| {np.linalg.norm(fd):.3e})")
+    run.close()
+    plan.close()
+    assert np.linalg.norm(fd) > 0 and err <= 1e-8
+
+
+def test_spectral_checkpoint_kind_and_sigma_reach():
+    """A spectral blob loads only as spectral (and a full one only as full); put_sigma takes
+    only steps the ring holds."""
+    import torch
+    import paper_2604_07170_amd as pa
+    from wfp_workloads import config
+    w = config(0)
+    dev = torch.device("cuda", 0)
+    plan = _plan(w, "fp64")
+    s = torch.ones(w.M, dtype=torch.float64, device=dev)
+    for _ in range(5):
+        plan.step(s)
+    spec, full = plan.save_spectral_state(), plan.save_state()
+    with pytest.raises(pa.Wfp2dError):
+        plan.load_state(spec)
+    with pytest.raises(pa.Wfp2dError):
+        plan.load_spectral_state(full)
+    plan.load_spectral_state(spec)
+    assert plan.info()["steps_ingested"] == 5
+    for bad in (0, 6):
+        with pytest.raises(pa.Wfp2dError):
+            plan.put_sigma(bad, s)
+    for l in range(1, 6):
+        plan.put_sigma(l, s)
+    plan.close()
 
 
 def test_state_save_load_and_reset():
