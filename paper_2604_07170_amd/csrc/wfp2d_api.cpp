@@ -659,7 +659,23 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     // moves by about ten times that bound, two orders of magnitude below tol; FP64 plans use
     // every stored term.
     p.local_terms = p.precision == WFP2D_PREC_MIXED ? local_table_terms(LT, p.tol) : kChebDeg;
-    if (p.local_fast && p.W <= 64 && pc_producers(p.n_reg, p.local_terms) > 0 && p.opts.local_pairs == 0)
+    {
+        // every regular panel k has exactly zero coefficients on the levels d < k (its nodes lie
+        // at delays >= k dt, and the centred stencils reach no further forward): the pair
+        // kernel's LDS-table form then stores and multiplies only the levels from each row
+        // block's first panel on
+        bool zero_below = true;
+        for (int sp = 0; sp < p.n_reg && zero_below; ++sp)
+            for (int d = 0; d < std::min(sp, LT.nlev) && zero_below; ++d)
+                for (int c = 0; c < p.local_terms; ++c)
+                    if (LT.coef[((size_t)sp * LT.nlev + d) * kChebDeg + c] != 0.0) {
+                        zero_below = false;
+                        break;
+                    }
+        p.pc_skip = zero_below ? 1 : 0;
+        p.pc_nprod = pc_producers(p.n_reg, p.local_terms, &p.pc_rb, LT.nlev, zero_below);
+    }
+    if (p.local_fast && p.W <= 64 && p.pc_nprod > 0 && p.opts.local_pairs == 0)
         build_pair_lists(p, cell_start, tcell_start);
     if (!p.local_pairs) p.local_terms = kChebDeg;
     if (p.local_pairs) {
@@ -677,17 +693,6 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
             }
         p.d_cpow = p.alloc<double>((int64_t)cpow.size());
         upload(p.d_cpow, cpow);
-        // the producer may skip MFMA k-steps below a row block's first panel when every
-        // regular panel k has exactly zero coefficients on the levels d < k
-        bool zero_below = true;
-        for (int sp = 0; sp < p.n_reg && zero_below; ++sp)
-            for (int d = 0; d < std::min(sp, nl) && zero_below; ++d)
-                for (int c = 0; c < D; ++c)
-                    if (cpow[((size_t)sp * kChebDeg + c) * nl + d] != 0.0) {
-                        zero_below = false;
-                        break;
-                    }
-        p.pc_skip = zero_below ? 1 : 0;
     }
     // local-pair count (reported; without pair lists the local kernel finds pairs through the cell lists)
     if (!p.local_pairs) {

@@ -37,12 +37,13 @@ constexpr int kPcLdsRows = 256;    //   rows of the variant with the power-basis
 // producer waves of the producer / consumer local kernel and its 16-row MFMA blocks per producer
 // (rb: 2 up to 384 rows, with the A operands held in registers; else 3, read from cache at each
 // item), at least 4 of its 16 waves left to evaluate pairs; 0 when the profile rows do not fit it
-// (rb 4: up to kPcLdsRows rows of 35 levels, the table in LDS and 4 producers, 12 waves left for
-// the pairs)
-inline int pc_producers(int n_reg, int terms, int *rb = nullptr, int nlev = 0)
+// (rb 4: up to kPcLdsRows rows of 35 levels, 4 producers, 12 waves left for the pairs, the table
+// in LDS without the levels below each row block's first panel, which must then be exactly zero:
+// zero_below)
+inline int pc_producers(int n_reg, int terms, int *rb = nullptr, int nlev = 0, bool zero_below = false)
 {
     const int rows = n_reg * terms, nblk = (rows + 15) / 16;
-    if (nlev == 35 && rows <= kPcLdsRows && terms % 2 == 0 && terms <= 16) {
+    if (nlev == 35 && zero_below && rows <= kPcLdsRows && terms % 2 == 0 && terms <= 16) {
         if (rb) *rb = 4;
         return 4;
     }
@@ -50,9 +51,29 @@ inline int pc_producers(int n_reg, int terms, int *rb = nullptr, int nlev = 0)
     if (rb) *rb = r;
     return (terms % 2 == 0 && rows <= kPcMaxRows && (r == 2 || terms == 20) && nprod <= 12) ? nprod : 0;
 }
-// dynamic LDS of the producer / consumer kernel: two profile buffers of up to kPcMaxRows rows
-constexpr size_t kPcDynLds = std::max((size_t)2 * 16 * (kPcMaxRows + 2) * 8,
-                                      (size_t)2 * 16 * (kPcLdsRows + 2) * 8 + (size_t)kPcLdsRows * 36 * 8);
+// Profile layout in LDS: the row of (source q, panel k) starts at q psi_src + k stride doubles.
+// With the table in LDS (rb 4) and 16 terms a panel's row is padded to 9 16-byte chunks, so the
+// rows of one source's panels start in different 16-byte bank groups (14 terms are 7 chunks
+// already; 12 terms stay unpadded).
+inline int pc_panel_stride(int rb, int terms) { return rb == 4 && terms == 16 ? 18 : terms; }
+inline int pc_psi_src(int rb, int n_reg, int terms) { return n_reg * pc_panel_stride(rb, terms) + 2; }
+// rb 4: first MFMA k-step of the rows [64 r, 64 r + 64) (block r of every producer), and the
+// doubles of the compacted table: rows of 4 (KS - kst) levels from level 4 kst on, each padded by
+// 2 doubles so that the 16 rows one MFMA operand reads fall in distinct LDS banks
+constexpr int pc_kst(int r, int terms) { return (64 * r / terms) / 4; }
+constexpr int pc_ctab_stride(int r, int terms, int ks) { return 4 * (ks - pc_kst(r, terms)) + 2; }
+constexpr int pc_ctab_doubles(int terms, int ks)
+{
+    return 64 * (pc_ctab_stride(0, terms, ks) + pc_ctab_stride(1, terms, ks) + pc_ctab_stride(2, terms, ks) +
+                 pc_ctab_stride(3, terms, ks));
+}
+// dynamic LDS of the producer / consumer kernel: two profile buffers, and with rb 4 the table
+constexpr size_t pc_lds_rb4(int terms)
+{
+    return (size_t)2 * 16 * (16 * (terms == 16 ? 18 : terms) + 2) * 8 + (size_t)pc_ctab_doubles(terms, 9) * 8;
+}
+constexpr size_t kPcDynLds = std::max(std::max((size_t)2 * 16 * (kPcMaxRows + 2) * 8, pc_lds_rb4(16)),
+                                      std::max(pc_lds_rb4(14), pc_lds_rb4(12)));
 // fixed device workspace of wfp2d_evaluate_noalloc (one per device, held until the process ends)
 constexpr size_t kScratchBytes = size_t(64) << 20;
 
@@ -223,6 +244,7 @@ struct Plan {
     int32_t *d_pair_dtg = nullptr, *d_pair_dsg = nullptr;   // pairs with r < dt/2: sorted target, source
     int64_t pair_ndy = 0;
     int32_t pc_skip = 0;              //   the regular panels' table is zero below each panel's level (MFMA k-steps skipped)
+    int32_t pc_rb = 0, pc_nprod = 0;  //   its variant: MFMA row blocks per producer, producer waves
     void *d_pc_desc = nullptr;        // producer / consumer kernel: item descriptors (32 bytes each)
     int32_t *d_pc_ioff = nullptr;     //   first item of each workgroup
     int32_t pc_grid = 0;              //   workgroups (one per CU); 0 = kernel not used

@@ -1559,8 +1559,7 @@ constexpr int kDescWords = 8;
 // RB 16-row MFMA blocks per producer wave; the A operands (the power-basis table) in registers
 // (RB == 2), in LDS (RB == 4: the table is staged once per launch), or read from cache (RB == 3).
 template <int NL, int NTERM, int RB>
-__global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g, int nprod,
-                                                   int skip)
+__global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, const int64_t *__restrict__ step, Geom g, int nprod)
 {
     // Every global load is issued at least one item before its value is used, and the loop
     // bodies have no data-dependent branches around loads or MFMAs, so the in-order wait on
@@ -1569,23 +1568,35 @@ __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, con
     constexpr bool kRegA = RB == 2, kLdsA = RB == 4;
     if (kLdsA) nprod = 4;                             // the LDS-table form always has four producers
     const int64_t m = step[0] - g.lookahead;
-    // dynamic LDS: [A table: kPcLdsRows x 4 KS (RB == 4)] then psi[2][kFastSrc][psiSrc] (16-byte rows)
+    // dynamic LDS: [A table (RB == 4): rows [64 r, 64 r + 64) hold the levels from 4 kst(r) on]
+    // then psi[2][kFastSrc][psiSrc] (16-byte rows; RB == 4 pads each panel's row, pc_panel_stride)
+    constexpr int PS = kLdsA && D == 16 ? 18 : D;     // doubles per panel row in psi (pc_panel_stride)
     extern __shared__ __align__(16) double lp_dyn[];
     double *const ctab = lp_dyn;
-    double *const lp_lds = lp_dyn + (kLdsA ? kPcLdsRows * 4 * KS : 0);
+    double *const lp_lds = lp_dyn + (kLdsA ? pc_ctab_doubles(D, KS) : 0);
     __shared__ double tacc[2][kPairTBPad];            // per-target sums of a (unit, batch), by parity
+    // compacted table: row stride and start of region r
+    auto ct_len = [](int r) { return pc_ctab_stride(r, D, KS); };
+    auto ct_off = [&](int r) {
+        int o = 0;
+        for (int rr = 0; rr < r; ++rr) o += 64 * ct_len(rr);
+        return o;
+    };
 
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
-    const int nrow = A.n_reg * D, psiSrc = A.n_reg * D + 2;
+    const int nrow = A.n_reg * D, psiSrc = A.n_reg * PS + 2;
     const int i0 = P.ioff[blockIdx.x], ni = P.ioff[blockIdx.x + 1] - i0;   // this workgroup's items
     const LpDesc *__restrict__ desc = P.desc + i0;
     auto item = [&](int t) { return lane_words(desc + min(t, ni - 1), kDescWords, lane); };   // in range when ni > 0
     for (int t = tid; t < 2 * kPairTBPad; t += 1024) (&tacc[0][0])[t] = 0.0;
     if (kLdsA)                                        // A table C[row][d], rows past the table and d >= NL zero
-        for (int e = tid; e < kPcLdsRows * 4 * KS; e += 1024) {
-            const int row = e / (4 * KS), d = e - row * (4 * KS);
-            ctab[e] = (row < nrow && d < NL) ? A.cpow[(size_t)((row / D) * kChebDeg + row % D) * NL + d] : 0.0;
-        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            for (int e = tid; e < 64 * ct_len(r); e += 1024) {
+                const int row = 64 * r + e / ct_len(r), j = e % ct_len(r), d = 4 * pc_kst(r, D) + j;
+                ctab[ct_off(r) + e] = (j < ct_len(r) - 2 && row < nrow && d < NL)
+                                          ? A.cpow[(size_t)((row / D) * kChebDeg + row % D) * NL + d] : 0.0;
+            }
     __syncthreads();
     if (ni == 0) return;                              // uniform, after the only barrier so far
 
@@ -1595,7 +1606,7 @@ __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, con
         // (zero for rows past the table: their MFMAs add nothing and their rows are not stored)
         auto a_op = [&](int r, int ks) {
             const int row = (wave + r * nprod) * 16 + (lane & 15), d = 4 * ks + (lane >> 4);
-            if (kLdsA) return ctab[row * (4 * KS) + d];
+            if (kLdsA) return ctab[ct_off(r) + (row - 64 * r) * ct_len(r) + (d - 4 * pc_kst(r, D))];   // ks >= kst(r)
             const int rr = min(row, nrow - 1), dd = min(d, NL - 1);
             const double v = A.cpow[(size_t)((rr / D) * kChebDeg + rr % D) * NL + dd];
             return (row < nrow && d < NL) ? v : 0.0;
@@ -1625,15 +1636,16 @@ __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, con
             mfma_d4 acc[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) acc[r] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-            if (kLdsA && skip) {
+            if (kLdsA) {
                 // A regular panel k weights only levels d >= k (its nodes lie at delays >= k dt and
-                // the centred stencils reach back, never forward, from there; the plan checks the
-                // table): block r holds panels >= (64 r)/D, so its k-steps below kst(r) are zero.
+                // the centred stencils reach back, never forward, from there; the plan takes this
+                // form only when its table has those zeros): block r holds panels >= (64 r)/D, so
+                // its k-steps below kst(r) are zero and the table does not hold them.
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                     for (int r = 0; r < RB; ++r)
-                        if (ks >= (64 * r / D) / 4)
+                        if (ks >= pc_kst(r, D))
                             acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_op(r, ks), bv[ks], acc[r], 0, 0, 0);
             } else {
 #pragma unroll
@@ -1643,14 +1655,28 @@ __global__ __launch_bounds__(1024) void k_local_pc(LocalArgs A, PairLists P, con
                         acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(kRegA ? ca[kRegA ? r : 0][ks] : a_op(r, ks), bv[ks], acc[r],
                                                                       0, 0, 0);
             }
-            // D[lane][e] = C[row = (wave + r nprod) 16 + lane / 16 + 4 e][q = lane % 16]; with nprod
-            // known at compile time the stores share one address register and immediate offsets
-            double *const dq = dst + (lane & 15) * psiSrc + wave * 16 + (lane >> 4);
+            // D[lane][e] = C[row = (wave + r nprod) 16 + lane / 16 + 4 e][q = lane % 16], stored at
+            // q psiSrc + (row / D) PS + row % D; with nprod known at compile time and PS = D the
+            // stores share one address register and immediate offsets
+            double *const dq = dst + (lane & 15) * psiSrc;
+            if constexpr (PS == D || D == 16) {
+                // a 16-row block is one panel (D = 16) or rows are dense: one base, immediate offsets
+                constexpr int BS = D == 16 ? PS : 16;  // psi doubles per 16-row block
+                double *const db = dq + wave * BS + (lane >> 4);
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
+                for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if ((lane >> 4) < nrow - (wave + r * nprod) * 16 - 4 * e) dq[r * nprod * 16 + 4 * e] = acc[r][e];
+                    for (int e = 0; e < 4; ++e)
+                        if ((lane >> 4) < nrow - (wave + r * nprod) * 16 - 4 * e) db[r * nprod * BS + 4 * e] = acc[r][e];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = (wave + r * nprod) * 16 + (lane >> 4) + 4 * e;
+                        if (row < nrow) dq[row + (row / D) * (PS - D)] = acc[r][e];
+                    }
+            }
         };
         load_b(bva, item(0));
         synth(bva, lp_lds);                           // item 0 -> buffer 0
@@ -2130,8 +2156,8 @@ hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt)
     B.dtg = p.d_pair_dtg;
     B.dsg = p.d_pair_dsg;
     B.ndy = p.pair_ndy;
-    B.psi_src = p.n_reg * p.local_terms + 2;
-    B.dterms = p.local_terms;
+    B.psi_src = pc_psi_src(p.pc_rb, p.n_reg, p.local_terms);
+    B.dterms = pc_panel_stride(p.pc_rb, p.local_terms);
     B.fill = fill ? 1 : 0;
     B.nlev = p.g.nlev;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(p.pair_n_work, 4096));
@@ -2152,15 +2178,13 @@ hipError_t launch_local(Plan &p)
 {
     const LocalArgs A = local_args(p);
     if (p.local_pairs) {
-        int rb = 2;
-        const int nprod = pc_producers(p.n_reg, p.local_terms, &rb, p.g.nlev);
+        const int rb = p.pc_rb, nprod = p.pc_nprod;
         const unsigned grid = (unsigned)p.pc_grid;
-        const int skip = p.pc_skip;
-        const size_t lds = (size_t)2 * kFastSrc * (p.n_reg * p.local_terms + 2) * sizeof(double) +
-                           (rb == 4 ? (size_t)kPcLdsRows * 4 * ((p.g.nlev + 3) / 4) * sizeof(double) : 0);
+        const size_t lds = (size_t)2 * kFastSrc * pc_psi_src(rb, p.n_reg, p.local_terms) * sizeof(double) +
+                           (rb == 4 ? (size_t)pc_ctab_doubles(p.local_terms, (p.g.nlev + 3) / 4) * sizeof(double) : 0);
         const PairLists P = pair_lists(p);
 #define WFP2D_LAUNCH_PC(NLV, NTV, RBV) \
-    hipLaunchKernelGGL((k_local_pc<NLV, NTV, RBV>), dim3(grid), dim3(1024), lds, p.stream, A, P, p.d_step, p.g, nprod, skip)
+    hipLaunchKernelGGL((k_local_pc<NLV, NTV, RBV>), dim3(grid), dim3(1024), lds, p.stream, A, P, p.d_step, p.g, nprod)
 #define WFP2D_LAUNCH_PC_NL(NTV, RBV) \
     do { if (p.g.nlev == 35) WFP2D_LAUNCH_PC(35, NTV, RBV); else WFP2D_LAUNCH_PC(43, NTV, RBV); } while (0)
         if (rb == 4 && p.local_terms == 16) WFP2D_LAUNCH_PC(35, 16, 4);
