@@ -150,6 +150,13 @@ def golden_samples(name: str):
     return out
 
 
+def init_phases(info: dict) -> dict:
+    """The plan's set-up time by phase (wfp2d_info.init_ms), in ms."""
+    names = ("modes_geometry", "nufft_point_data", "history_tables", "local_tables", "device_memory",
+             "pair_lists", "total")
+    return {n: round(v, 1) for n, v in zip(names, info.get("init_ms", [0.0] * 7))}
+
+
 def timed_window(nt: int, LA: int, W: int, K: int):
     """First and last reported step of the timed window: the window ends at the workload's
     last step nt (extended past it when K steps would reach back before the far history
@@ -611,7 +618,8 @@ def main():
                 "hbm_roofline_step_frac": round(r["hbm_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                 "sample_rel_err_vs_oracle": r["stored"]["rel_l2"] if r["stored"] else live_err.get(f),
                 "stored_oracle_check": r["stored"], "live_oracle_rel_err": live_err.get(f),
-                "plan_init_s": round(r["init_s"], 2), "stages": r["per_stage"]}
+                "plan_init_s": round(r["init_s"], 2), "plan_init_ms": init_phases(r["info"]),
+                "stages": r["per_stage"]}
 
     head_f = forms[0]
     h = results[head_f]
@@ -644,6 +652,7 @@ def main():
         "hbm_roofline_step_frac": hs["hbm_roofline_step_frac"],
         "hbm_copy_GBs": round(copy_gbs, 1),
         "plan_init_s": hs["plan_init_s"],
+        "plan_init_ms": hs["plan_init_ms"],
         "stages": hs["stages"],
         "cpu_baseline": cpu,
         "sample_rel_err_vs_oracle": hs["sample_rel_err_vs_oracle"],
@@ -654,7 +663,7 @@ def main():
         s = summary(f)
         out[f] = {k: s[k] for k in ("value", "ms_per_step", "roofline", "hbm_roofline_step_frac",
                                     "sample_rel_err_vs_oracle", "stored_oracle_check", "live_oracle_rel_err",
-                                    "plan_init_s", "stages")}
+                                    "plan_init_s", "plan_init_ms", "stages")}
         out[f"{head_f}_over_{f}"] = round(hs["value"] / s["value"], 3)
     errs = [e for e in [hs["sample_rel_err_vs_oracle"]] + [out[f]["sample_rel_err_vs_oracle"] for f in forms[1:]]
             if e is not None]

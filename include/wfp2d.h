@@ -135,6 +135,13 @@ typedef struct {
     int64_t local_pair_words;    /* entries of the stored regular pair lists: pairs with r >= dt/2 and
                                     the padding that completes each (source, sub-panel) group to whole
                                     runs of 8 (0 if none) */
+    double init_ms[7];           /* wall-clock ms of the plan's set-up: 0 modes and geometry
+                                    (cell sort), 1 NUFFT point data (kernel origins and
+                                    weights, tile lists), 2 history tables (blend, SOE nodes,
+                                    Hankel coefficients of eq. H, window FIR), 3 local-weight
+                                    tables and NUFFT corrections, 4 device memory and uploads,
+                                    5 pair lists, power-basis table and kernel attributes;
+                                    6 total */
 } wfp2d_info;
 
 /* Fill *opts with the defaults listed above.  Never fails for a valid pointer. */
@@ -224,7 +231,10 @@ const char *wfp2d_last_error(wfp2d_plan plan);
  *   (each complex, packed half-disk order of wfp2d_debug_modes, in the plan's
  *    FP32 (mixed) or FP64 precision, interleaved re/im);
  *   4 = u_h at t_m, 5 = u_l at t_m (float64 [Nx], target order);
- *   6 = the stored modes (n_x, n_y) as int32 pairs [n_modes][2].
+ *   6 = the stored modes (n_x, n_y) as int32 pairs [n_modes][2];
+ *   7 = per distinct |k| of the far modes (n_far_classes rows): kappa, then its 640
+ *       Hankel coefficients H_l(kappa) of eq. H as the plan computed them on the
+ *       device, float64 [n_far_classes][641].
  * dst: host pointer of at least *bytes bytes; on return *bytes = bytes written.
  * Errors: ERR_ARG (unknown what, short buffer), ERR_DEVICE. */
 wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t *bytes);

@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
                                                  "steps_ingested", "step_reported")]
                 + [("precision", ctypes.c_int32), ("n_regular_subpanels", ctypes.c_int32),
                    ("spread_tile", ctypes.c_int32), ("local_path", ctypes.c_int32),
-                   ("local_pair_bytes", ctypes.c_int64), ("local_pair_words", ctypes.c_int64)])
+                   ("local_pair_bytes", ctypes.c_int64), ("local_pair_words", ctypes.c_int64),
+                   ("init_ms", ctypes.c_double * 7)])
 
 
 _lib = None
@@ -146,6 +147,7 @@ class StageNames:
     U_H: int = 4
     U_L: int = 5
     MODES: int = 6
+    HANKEL: int = 7
 
 
 STAGE = StageNames()
@@ -207,7 +209,9 @@ class Wfp2d:
     def info(self) -> dict:
         inf = Info()
         self._check(self.lib.wfp2d_query(self.h, ctypes.byref(inf)))
-        return {name: getattr(inf, name) for name, _ in Info._fields_}
+        out = {name: getattr(inf, name) for name, _ in Info._fields_}
+        out["init_ms"] = list(out["init_ms"])
+        return out
 
     # -- the hot path --
     def step(self, sigma):
@@ -383,6 +387,8 @@ class Wfp2d:
             buf = np.zeros(self.Nx, np.float64)
         elif what == STAGE.MODES:
             buf = np.zeros((inf["n_modes"], 2), np.int32)
+        elif what == STAGE.HANKEL:
+            buf = np.zeros((inf["n_far_classes"], 641), np.float64)
         else:
             real = np.float32 if inf["precision"] == PREC_MIXED else np.float64
             buf = np.zeros(2 * inf["n_modes"], real)

@@ -1,5 +1,6 @@
 // Plan construction, step / evaluate orchestration and the C ABI of wfp2d.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -317,6 +318,15 @@ static void build_pair_lists(Plan &p, const std::vector<int32_t> &cell_start, co
 
 static void build(Plan &p, const double *src_xy, const double *tgt_xy)
 {
+    // wall-clock time of the set-up phases (wfp2d_info.init_ms)
+    using clk = std::chrono::steady_clock;
+    const clk::time_point t_start = clk::now();
+    clk::time_point t_mark = t_start;
+    auto phase = [&](int k) {
+        const clk::time_point now = clk::now();
+        p.init_ms[k] += std::chrono::duration<double, std::milli>(now - t_mark).count();
+        t_mark = now;
+    };
     hip_check(hipSetDevice(p.device), "hipSetDevice");
     hip_check(scratch_address(p.device, &p.scratch), "hipGetSymbolAddress of the fixed workspace");
     {
@@ -458,28 +468,26 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         tcell_sorted[i] = tcell[tperm[i]];
     }
 
+    phase(0);                                         // modes and geometry
     // spreading / interpolation kernel data, tile lists
     const double gscale = p.dk * g.nf / (2.0 * M_PI);
-    auto kernel_data = [&](const std::vector<double2> &pts, std::vector<int2> &base, std::vector<double> &wts) {
+    auto kernel_data = [&](const std::vector<double2> &pts, std::vector<int2> &base) {
         const int64_t n = (int64_t)pts.size();
+        // the origins here; the 2w kernel weights per point on the device (k_es_weights)
         base.resize(n);
-        wts.resize((size_t)n * 2 * w);
+        bool inside = true;
+#pragma omp parallel for schedule(static) reduction(&& : inside)
         for (int64_t j = 0; j < n; ++j) {
             double gx = pts[j].x * gscale, gy = pts[j].y * gscale;
             int64_t l0x = (int64_t)std::ceil(gx - 0.5 * w), l0y = (int64_t)std::ceil(gy - 0.5 * w);
             base[j] = make_int2((int)(l0x - g.lmin), (int)(l0y - g.lmin));
-            if (base[j].x < 0 || base[j].y < 0 || base[j].x + w > g.Lpad || base[j].y + w > g.Lpad)
-                fail(WFP2D_ERR_DOMAIN, "point outside the spreading band");
-            for (int a2 = 0; a2 < w; ++a2) {
-                wts[(size_t)j * 2 * w + a2] = es_kernel((double)(l0x + a2) - gx, w, p.es_beta);
-                wts[(size_t)j * 2 * w + w + a2] = es_kernel((double)(l0y + a2) - gy, w, p.es_beta);
-            }
+            inside = inside && !(base[j].x < 0 || base[j].y < 0 || base[j].x + w > g.Lpad || base[j].y + w > g.Lpad);
         }
+        if (!inside) fail(WFP2D_ERR_DOMAIN, "point outside the spreading band");
     };
     std::vector<int2> sbase, tbase;
-    std::vector<double> swts, twts;
-    kernel_data(sxy, sbase, swts);
-    kernel_data(txy, tbase, twts);
+    kernel_data(sxy, sbase);
+    kernel_data(txy, tbase);
     const int ntile = g.ntx * g.ntx;
     p.h_src_base = sbase;
     build_spread_tiles(p, p.spread_tile);
@@ -490,22 +498,18 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         for (int t = 0; t < ntile; ++t) off[t + 1] += off[t];
         std::vector<int32_t> pos(off.begin(), off.end() - 1);
         for (int64_t i = 0; i < Nx; ++i) lst[pos[(tbase[i].y / kTile) * g.ntx + tbase[i].x / kTile]++] = (int32_t)i;
-        // origins and weights in this processing order, so that the interpolation kernel
-        // reads them without waiting for the target index
+        // origins (and, on the device, weights) in this processing order, so that the
+        // interpolation kernel reads them without waiting for the target index
         std::vector<int2> tb(Nx);
-        std::vector<double> tw(twts.size());
-        for (int64_t e = 0; e < Nx; ++e) {
-            tb[e] = tbase[lst[e]];
-            std::copy(twts.begin() + (size_t)lst[e] * 2 * w, twts.begin() + (size_t)(lst[e] + 1) * 2 * w, tw.begin() + (size_t)e * 2 * w);
-        }
+        for (int64_t e = 0; e < Nx; ++e) tb[e] = tbase[lst[e]];
         tbase.swap(tb);
-        twts.swap(tw);
         p.d_ttile_off = p.alloc<int32_t>(ntile + 1);
         upload(p.d_ttile_off, off);
         p.d_ttile_tgt = p.alloc<int32_t>(Nx);
         upload(p.d_ttile_tgt, lst);
     }
 
+    phase(1);                                         // NUFFT point data
     // ---------------- tables ----------------
     Blend phi(p.delta, p.b, 160);
     std::vector<double> phi_in(p.W + 1);
@@ -517,21 +521,45 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     soe_nodes(lam, qw);
     std::vector<double> kap(p.n_classes);
     for (int64_t c = 0; c < p.n_classes; ++c) kap[c] = p.dk * std::sqrt((double)keys[c]);
-    std::vector<double> H;
-    hankel_table(kap, p.A, p.Delta, p.b_Delta, lam, qw, H);
+    p.h_class_kappa = kap;
+    // Hankel coefficients of eq. H, one row per distinct |k|^2 of the far modes: the quadrature
+    // in r on the host, the contraction with J0(kappa r) on the device (k_hankel)
+    std::vector<double> H((size_t)p.n_classes * kNsoe);
+    p.d_H = p.alloc<double>(std::max<int64_t>(1, p.n_classes * kNsoe));
+    if (p.n_classes > 0) {
+        std::vector<double> hr, hE;
+        hankel_quadrature(p.A, p.Delta, p.b_Delta, lam, qw, hr, hE);
+        double *d_kap = p.alloc<double>(p.n_classes), *d_r = p.alloc<double>((int64_t)hr.size());
+        double *d_E = p.alloc<double>((int64_t)hE.size());
+        upload(d_kap, kap);
+        upload(d_r, hr);
+        upload(d_E, hE);
+        hip_check(launch_hankel(p, d_kap, p.n_classes, d_r, (int)hr.size(), d_E, kNsoe, p.d_H), "Hankel coefficients");
+        hip_check(hipMemcpyAsync(H.data(), p.d_H, H.size() * sizeof(double), hipMemcpyDeviceToHost, p.stream), "copy");
+        hip_check(p.stream ? hipStreamSynchronize(p.stream) : hipDeviceSynchronize(), "synchronize");
+        p.release(d_kap);
+        p.release(d_r);
+        p.release(d_E);
+    }
     std::vector<double> dec(kNsoe), inj(kNsoe), chi((size_t)p.n_classes * (p.W - 1));
     for (int l = 0; l < kNsoe; ++l) {
         dec[l] = std::exp(-lam[l] * p.dt);
         inj[l] = p.dt * std::exp(-lam[l] * ((double)(p.LA + p.W - 1) * p.dt - p.A));
     }
+    // window FIR per class: chi[c][i] = (1 - phi) sum_l H[c][l] dt e^{-lambda_l ((LA + 1 + i) dt - A)}
+    std::vector<double> fir((size_t)(p.W - 1) * kNsoe);
+    for (int i = 0; i < p.W - 1; ++i)
+        for (int l = 0; l < kNsoe; ++l)
+            fir[(size_t)i * kNsoe + l] = p.dt * std::exp(-lam[l] * ((double)(p.LA + 1 + i) * p.dt - p.A));
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < p.n_classes; ++c)
         for (int i = 0; i < p.W - 1; ++i) {
-            double s = 0.0, wwin = 1.0 - phi_in[p.W - 1 - i];
-            for (int l = 0; l < kNsoe; ++l)
-                s += H[(size_t)c * kNsoe + l] * p.dt * std::exp(-lam[l] * ((double)(p.LA + 1 + i) * p.dt - p.A));
-            chi[(size_t)c * (p.W - 1) + i] = s * wwin;
+            double s = 0.0;
+            for (int l = 0; l < kNsoe; ++l) s += H[(size_t)c * kNsoe + l] * fir[(size_t)i * kNsoe + l];
+            chi[(size_t)c * (p.W - 1) + i] = s * (1.0 - phi_in[p.W - 1 - i]);
         }
 
+    phase(2);                                         // history tables
     const int lev_min = -p.lookahead;
     LocalWeights LW(p.dt, p.W, p.p, lev_min, phi);
     LocalTable LT = build_local_table(LW, 40, 1e-11);
@@ -560,6 +588,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         tw[2 * j + 1] = std::sin(2.0 * M_PI * (double)j / (double)g.nf);
     }
 
+    phase(3);                                         // local tables, NUFFT corrections
     // ---------------- device memory ----------------
     const int64_t sr = p.sizeof_real;
     g.lookahead = p.lookahead;
@@ -575,10 +604,14 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_tgt_xy, txy);
     p.d_src_base = p.alloc<int2>(M);
     upload(p.d_src_base, sbase);
-    p.d_src_wts = upload_real(p, swts);
     p.d_tgt_base = p.alloc<int2>(Nx);
     upload(p.d_tgt_base, tbase);
-    p.d_tgt_wts = upload_real(p, twts);
+    // exponential-of-semicircle weights of every source (sorted order) and target (processing
+    // order), 2w per point, in the grid precision
+    p.d_src_wts = p.alloc<char>(M * 2 * w * sr);
+    p.d_tgt_wts = p.alloc<char>(Nx * 2 * w * sr);
+    hip_check(launch_es_weights(p, p.d_src_xy, nullptr, p.d_src_base, M, gscale, p.d_src_wts), "source weights");
+    hip_check(launch_es_weights(p, p.d_tgt_xy, p.d_ttile_tgt, p.d_tgt_base, Nx, gscale, p.d_tgt_wts), "target weights");
     p.d_grid = p.alloc<char>((int64_t)g.Lpad * g.Lpad * 2 * sr);
     p.d_T1 = p.alloc<char>((int64_t)g.Lpad * N * 2 * sr);
     p.d_T1t = p.alloc<char>((int64_t)g.Lpad * N * 2 * sr);
@@ -606,8 +639,7 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     upload(p.d_far_pk, far_pk);
     p.d_far_cls = p.alloc<int32_t>(p.n_far);
     upload(p.d_far_cls, far_cls);
-    p.d_H = p.alloc<double>(p.n_classes * kNsoe);
-    upload(p.d_H, H);
+    // d_H holds the Hankel table computed above
     p.d_chi = p.alloc<double>(p.n_classes * (p.W - 1));
     upload(p.d_chi, chi);
     p.d_dec = p.alloc<double>(kNsoe);
@@ -658,6 +690,8 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
     // coefficient (the scale of the fit criterion of the tables).  Measured, the field then
     // moves by about ten times that bound, two orders of magnitude below tol; FP64 plans use
     // every stored term.
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    phase(4);                                         // device memory and uploads
     p.local_terms = p.precision == WFP2D_PREC_MIXED ? local_table_terms(LT, p.tol) : kChebDeg;
     {
         // every regular panel k has exactly zero coefficients on the levels d < k (its nodes lie
@@ -734,9 +768,12 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
                     {p.d_C, (size_t)p.n_modes * sizeof(double2)},
                     {p.d_atot, (size_t)p.n_modes * 2 * sr},
                     {p.d_B, (size_t)p.n_far * kNsoe * sizeof(double2)}};
+    phase(5);                                         // pair lists and the power-basis table
     hip_check(fft_setup(p), "FFT kernel attributes");
     hip_check(kernel_setup(p), "local kernel attributes");
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize after set-up");
+    phase(5);
+    p.init_ms[6] = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
 }
 
 // One step: a fixed sequence of launches whose arguments do not depend on the
@@ -1280,6 +1317,7 @@ wfp2d_status wfp2d_query(wfp2d_plan plan, wfp2d_info *info)
     info->local_path = p.local_pairs ? 2 : p.local_fast ? 1 : 0;
     info->local_pair_bytes = p.pair_bytes;
     info->local_pair_words = p.local_pairs ? p.pair_nword : 0;
+    for (int k = 0; k < 7; ++k) info->init_ms[k] = p.init_ms[k];
     info->n_regular_subpanels = p.n_reg;
     if (nonfinite) {
         p.err = "non-finite samples were ingested (taken as 0)";
@@ -1328,6 +1366,20 @@ wfp2d_status wfp2d_debug_copy(wfp2d_plan plan, int32_t what, void *dst, int64_t 
             for (int64_t i = 0; i < p.Nx; ++i) outv[i] = tmp[rank[i]];
             std::memcpy(dst, outv.data(), 8 * p.Nx);
             *bytes = 8 * p.Nx;
+            return WFP2D_OK;
+        }
+        case 7: {
+            // per distinct |k| of the far modes: kappa, then its 640 Hankel coefficients (device table)
+            const size_t row = 1 + kNsoe, need = (size_t)p.n_classes * row * sizeof(double);
+            if ((size_t)*bytes < need) fail(WFP2D_ERR_ARG, "destination too small");
+            std::vector<double> H((size_t)p.n_classes * kNsoe);
+            hip_check(hipMemcpy(H.data(), p.d_H, H.size() * sizeof(double), hipMemcpyDeviceToHost), "copy");
+            double *o = (double *)dst;
+            for (int64_t c = 0; c < p.n_classes; ++c) {
+                o[c * row] = p.h_class_kappa[c];
+                std::memcpy(o + c * row + 1, &H[(size_t)c * kNsoe], kNsoe * sizeof(double));
+            }
+            *bytes = (int64_t)need;
             return WFP2D_OK;
         }
         case 6: {

@@ -122,6 +122,11 @@ hipError_t launch_fft_rows2(Plan &p);
 hipError_t launch_interp(Plan &p);
 hipError_t launch_local(Plan &p);
 hipError_t launch_pairs_build(Plan &p, bool fill, int64_t *cnt, int64_t *dcnt);
+// NUFFT kernel weights of n points (2w each, grid precision; idx: optional point order)
+hipError_t launch_es_weights(Plan &p, const double2 *xy, const int32_t *idx, const int2 *base, int64_t n, double gscale,
+                             void *wts);
+// Hankel coefficients H[c][l] = sum_g J0(kappa_c r_g) E[l][g] (device pointers)
+hipError_t launch_hankel(Plan &p, const double *kappa, int64_t nk, const double *r, int nr, const double *E, int L, double *H);
 hipError_t launch_zero_f64(Plan &p, double *ptr, int64_t n);
 hipError_t launch_combine_dot(Plan &p, const double *wts, double *acc);
 hipError_t launch_combine(Plan &p, double *u_out);
@@ -245,6 +250,8 @@ struct Plan {
     int64_t pair_ndy = 0;
     int32_t pc_skip = 0;              //   the regular panels' table is zero below each panel's level (MFMA k-steps skipped)
     int32_t pc_rb = 0, pc_nprod = 0;  //   its variant: MFMA row blocks per producer, producer waves
+    double init_ms[7] = {};           // set-up phases (wfp2d_info.init_ms)
+    std::vector<double> h_class_kappa; // |k| of each distinct far-mode class (rows of d_H)
     void *d_pc_desc = nullptr;        // producer / consumer kernel: item descriptors (32 bytes each)
     int32_t *d_pc_ioff = nullptr;     //   first item of each workgroup
     int32_t pc_grid = 0;              //   workgroups (one per CU); 0 = kernel not used

@@ -1830,6 +1830,83 @@ __global__ __launch_bounds__(256) void k_local_dyadic(LocalArgs A, PairLists P, 
 
 // Grid-stride fill: a dispatch covers at most 2^32 work-items, and the sigma
 // ring alone can exceed that (4.3e9 doubles at 10^6 sources).
+// Exponential-of-semicircle weights of the NUFFT kernel (R18), psi(z) = exp(beta (sqrt(1 - (2z/w)^2)
+// - 1)) for |z| <= w/2, at the w grid offsets of each point's stencil in x and in y: point e
+// (coordinates xy[idx[e]], or xy[e] without idx) with origin base[e] (relative to lmin).
+template <class R>
+__global__ __launch_bounds__(256) void k_es_weights(const double2 *__restrict__ xy, const int32_t *__restrict__ idx,
+                                                    const int2 *__restrict__ base, int64_t n, double gscale, int lmin,
+                                                    int w, double beta, R *__restrict__ wts)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double2 pt = xy[idx ? idx[e] : e];
+    const double gx = pt.x * gscale, gy = pt.y * gscale;
+    const int2 b = base[e];
+    auto psi = [&](double z) {
+        const double t = 2.0 * z / w, a = 1.0 - t * t;
+        return a < 0.0 ? 0.0 : exp(beta * (sqrt(a) - 1.0));
+    };
+    for (int a2 = 0; a2 < w; ++a2) {
+        wts[e * 2 * w + a2] = (R)psi((double)(b.x + lmin + a2) - gx);
+        wts[e * 2 * w + w + a2] = (R)psi((double)(b.y + lmin + a2) - gy);
+    }
+}
+
+hipError_t launch_es_weights(Plan &p, const double2 *xy, const int32_t *idx, const int2 *base, int64_t n, double gscale,
+                             void *wts)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (p.precision == WFP2D_PREC_MIXED)
+        hipLaunchKernelGGL(k_es_weights<float>, dim3(nb), dim3(256), 0, p.stream, xy, idx, base, n, gscale, (int)p.g.lmin, p.g.w,
+                           p.es_beta, (float *)wts);
+    else
+        hipLaunchKernelGGL(k_es_weights<double>, dim3(nb), dim3(256), 0, p.stream, xy, idx, base, n, gscale, (int)p.g.lmin,
+                           p.g.w, p.es_beta, (double *)wts);
+    return hipGetLastError();
+}
+
+// Hankel coefficients of eq. H on the device: H[c][l] = sum_g J0(kappa_c r_g) E[l][g], the
+// quadrature nodes r and weights-with-kernel E from hankel_quadrature.  One workgroup per 16
+// classes x 64 SOE terms; the nodes in chunks of 64 with J0 and E staged in LDS (E rows padded
+// to 65 doubles: the 16 rows a wave reads fall in distinct banks).
+constexpr int kHkC = 16, kHkL = 64, kHkG = 64;
+__global__ __launch_bounds__(256) void k_hankel(const double *__restrict__ kappa, int64_t nk, const double *__restrict__ r,
+                                                int nr, const double *__restrict__ E, int L, double *__restrict__ H)
+{
+    __shared__ double sJ[kHkC][kHkG];
+    __shared__ double sE[kHkL][kHkG + 1];
+    const int tid = threadIdx.x, cl = tid >> 4, lq = tid & 15;
+    const int64_t c0 = (int64_t)blockIdx.x * kHkC;
+    const int l0 = blockIdx.y * kHkL;
+    double acc[kHkL / 16] = {0.0, 0.0, 0.0, 0.0};
+    for (int g0 = 0; g0 < nr; g0 += kHkG) {
+        for (int e = tid; e < kHkC * kHkG; e += 256) {
+            const int ci = e / kHkG, gi = e % kHkG;
+            const int64_t c = c0 + ci;
+            sJ[ci][gi] = (c < nk && g0 + gi < nr) ? j0(kappa[c] * r[g0 + gi]) : 0.0;
+        }
+        for (int e = tid; e < kHkL * kHkG; e += 256) {
+            const int li = e / kHkG, gi = e % kHkG;
+            sE[li][gi] = (l0 + li < L && g0 + gi < nr) ? E[(size_t)(l0 + li) * nr + g0 + gi] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int gi = 0; gi < kHkG; ++gi) {
+            const double j = sJ[cl][gi];
+#pragma unroll
+            for (int k = 0; k < kHkL / 16; ++k) acc[k] = fma(j, sE[lq + 16 * k][gi], acc[k]);
+        }
+        __syncthreads();
+    }
+    const int64_t c = c0 + cl;
+    if (c < nk)
+#pragma unroll
+        for (int k = 0; k < kHkL / 16; ++k)
+            if (l0 + lq + 16 * k < L) H[c * L + l0 + lq + 16 * k] = acc[k];
+}
+
 __global__ void k_zero_f64(double *__restrict__ p, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -2219,6 +2296,14 @@ hipError_t launch_local(Plan &p)
     }
     hipLaunchKernelGGL(k_local, dim3((unsigned)std::min<int64_t>((int64_t)p.ncell * p.ncell, 65536)), dim3(kLocalThreads), 0,
                        p.stream, A, p.d_step, p.g);
+    return hipGetLastError();
+}
+
+hipError_t launch_hankel(Plan &p, const double *kappa, int64_t nk, const double *r, int nr, const double *E, int L, double *H)
+{
+    if (nk == 0) return hipSuccess;
+    const dim3 grid((unsigned)((nk + kHkC - 1) / kHkC), (unsigned)((L + kHkL - 1) / kHkL));
+    hipLaunchKernelGGL(k_hankel, grid, dim3(256), 0, p.stream, kappa, nk, r, nr, E, L, H);
     return hipGetLastError();
 }
 

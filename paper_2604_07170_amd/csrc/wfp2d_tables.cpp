@@ -185,8 +185,8 @@ void soe_nodes(std::vector<double> &lam, std::vector<double> &q)
 //   H_l = q_l e^{-A lam_l} int_0^A J0(kappa r) I0(lam_l r) phi_Delta(A - r) r dr
 // by composite Gauss-Legendre in r (panels of width 0.02, 16 nodes).
 // ---------------------------------------------------------------------------
-void hankel_table(const std::vector<double> &kappa, double A, double Delta, double b_Delta,
-                  const std::vector<double> &lam, const std::vector<double> &q, std::vector<double> &H)
+void hankel_quadrature(double A, double Delta, double b_Delta, const std::vector<double> &lam, const std::vector<double> &q,
+                       std::vector<double> &r, std::vector<double> &E)
 {
     Blend phiD(Delta, b_Delta, 200);
     std::vector<double> x, w;
@@ -194,18 +194,28 @@ void hankel_table(const std::vector<double> &kappa, double A, double Delta, doub
     const int npan = (int)std::ceil(A / 0.02);
     const double h = A / npan;
     const int nr = npan * 16;
-    std::vector<double> r(nr), wr(nr);
+    std::vector<double> wr(nr);
+    r.resize(nr);
     for (int pnl = 0; pnl < npan; ++pnl)
         for (int i = 0; i < 16; ++i) {
             r[pnl * 16 + i] = (pnl + 0.5) * h + 0.5 * h * x[i];
             wr[pnl * 16 + i] = 0.5 * h * w[i];
         }
     const int L = (int)lam.size();
-    std::vector<double> E((size_t)L * nr);
+    E.resize((size_t)L * nr);
+#pragma omp parallel for schedule(static)
     for (int l = 0; l < L; ++l)
         for (int g = 0; g < nr; ++g)
             E[(size_t)l * nr + g] = q[l] * bessel_i0(lam[l] * r[g]) * std::exp(-A * lam[l]) *
                                     phiD.phi(A - r[g]) * r[g] * wr[g];
+}
+
+void hankel_table(const std::vector<double> &kappa, double A, double Delta, double b_Delta,
+                  const std::vector<double> &lam, const std::vector<double> &q, std::vector<double> &H)
+{
+    std::vector<double> r, E;
+    hankel_quadrature(A, Delta, b_Delta, lam, q, r, E);
+    const int nr = (int)r.size(), L = (int)lam.size();
     const int64_t nk = (int64_t)kappa.size();
     H.assign((size_t)nk * L, 0.0);
 #pragma omp parallel for schedule(dynamic, 4)

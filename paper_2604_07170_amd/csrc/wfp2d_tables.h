@@ -32,6 +32,11 @@ Params derive_params(double dt, int W, double tol, double Delta, double a_in, do
                      int lookahead_in);
 
 void soe_nodes(std::vector<double> &lam, std::vector<double> &q);
+// Quadrature of eq. H in r (composite Gauss-Legendre, panels of width 0.02, 16 nodes): nodes r[g]
+// and E[l][g] = q_l I0(lambda_l r_g) e^{-A lambda_l} phi_Delta(A - r_g) r_g w_g, so that
+// H_l(kappa) = sum_g J0(kappa r_g) E[l][g] (the contraction runs on the device in a plan)
+void hankel_quadrature(double A, double Delta, double b_Delta, const std::vector<double> &lam, const std::vector<double> &q,
+                       std::vector<double> &r, std::vector<double> &E);
 void hankel_table(const std::vector<double> &kappa, double A, double Delta, double b_Delta,
                   const std::vector<double> &lam, const std::vector<double> &q, std::vector<double> &H);
 
