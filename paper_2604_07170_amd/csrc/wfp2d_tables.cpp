@@ -311,6 +311,8 @@ static void fit_subpanel(const LocalWeights &LW, const SubPanel &s, double *coef
 {
     const int D = kChebDeg, nl = LW.nlev;
     std::vector<double> vals((size_t)D * nl);
+    // the weights at the D Chebyshev nodes, one node per thread (each writes its own row)
+#pragma omp parallel for schedule(dynamic, 1)
     for (int q = 0; q < D; ++q) {
         double x = std::cos(M_PI * (q + 0.5) / D);
         LW.eta(subpanel_r(s, x), &vals[(size_t)q * nl]);
@@ -359,7 +361,7 @@ LocalTable build_local_table(const LocalWeights &LW, int n_dy, double rel_tol)
     T.nlev = nl;
     T.panel_base.assign(LW.W, 0);
     T.panel_l2n.assign(LW.W, 0);
-    std::vector<double> coef, tmp((size_t)nl * D), ev(nl);
+    std::vector<double> coef, tmp((size_t)nl * D);
     // Fit error is judged against max(scale of the panel, 1e-2 x scale of the
     // largest weights): pairs near r = delta carry weights ~1e-5 of those at
     // small r, so their absolute accuracy, not their relative one, matters.
@@ -375,13 +377,20 @@ LocalTable build_local_table(const LocalWeights &LW, int n_dy, double rel_tol)
             for (int s = 0; s < ns; ++s) {
                 SubPanel sp = make_sub(r0 + (r1 - r0) * s / ns, r0 + (r1 - r0) * (s + 1) / ns, c);
                 fit_subpanel(LW, sp, &cf[(size_t)s * nl * D]);
-                for (double x : {-0.93, -0.61, -0.27, 0.05, 0.41, 0.77, 0.97}) {
-                    LW.eta(subpanel_r(sp, x), ev.data());
-                    for (int d = 0; d < nl; ++d) {
-                        double v = cheb_eval(&cf[((size_t)s * nl + d) * D], D, x);
-                        err = std::max(err, std::fabs(v - ev[d]));
-                        scale = std::max(scale, std::fabs(ev[d]));
-                    }
+            }
+            // fit error at 7 interior points of every sub-panel (maxima: the same in any order)
+            static const double xs[7] = {-0.93, -0.61, -0.27, 0.05, 0.41, 0.77, 0.97};
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : err, scale)
+            for (int sx = 0; sx < ns * 7; ++sx) {
+                const int s = sx / 7;
+                const double x = xs[sx % 7];
+                SubPanel sp = make_sub(r0 + (r1 - r0) * s / ns, r0 + (r1 - r0) * (s + 1) / ns, c);
+                std::vector<double> evs(nl);
+                LW.eta(subpanel_r(sp, x), evs.data());
+                for (int d = 0; d < nl; ++d) {
+                    double v = cheb_eval(&cf[((size_t)s * nl + d) * D], D, x);
+                    err = std::max(err, std::fabs(v - evs[d]));
+                    scale = std::max(scale, std::fabs(evs[d]));
                 }
             }
             global_scale = std::max(global_scale, scale);
