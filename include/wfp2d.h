@@ -77,7 +77,7 @@ typedef struct {
                          sum-of-exponentials validity range T <~ 3e4 (Sec. 2.3). */
     int32_t device;   /* HIP device ordinal */
     void *stream;     /* hipStream_t for every launch (NULL = default stream) */
-    int32_t spread_tile; /* type-1 spreading tile shape, 0 = default (3); see wfp2d_set_spread_tile */
+    int32_t spread_tile; /* type-1 spreading tile shape, 0 = default (6); see wfp2d_set_spread_tile */
     /* Local part (Sec. 6, eq. local2): 0 (default) = store the list of source-target
      * pairs with r < delta, with each pair's time-step panel and Chebyshev coordinate,
      * once at init (8 bytes per pair; 4 bytes plus one weight per lookup level for the
@@ -343,7 +343,11 @@ wfp2d_status wfp2d_batch_destroy(wfp2d_batch batch);
 /*
  * Spreading tile shape of the type-1 NUFFT (eq. sighat: the sources' kernel
  * contributions are summed per tile of the fine grid in on-chip memory).
- * code 1..5 = 8x8, 16x8, 16x16, 32x16, 32x32 fine-grid points.  The result
+ * code 1..5 = 8x8, 16x8, 16x16, 32x16, 32x32 fine-grid points summed on the
+ * vector units; code 6 = 16x16 tiles summed as a contraction over the tile's
+ * sources on the matrix cores (the kernel is a tensor product, so a tile's
+ * grid values are the product of the sources' y-weight columns, scaled by the
+ * samples, with their x-weight rows; requires w <= 16).  The result
  * does not depend on the shape (up to the order of floating-point sums); the
  * speed does, with the source density, so an autotuner picks it by timing.
  * wfp2d_set_spread_tile rebuilds the plan's per-tile source lists (it

@@ -338,7 +338,7 @@ class Wfp2d:
         self._check(self.lib.wfp2d_put_sigma(self.h, int(l), ctypes.c_void_p(sigma.data_ptr())))
 
     # -- spreading tile shape (autotuned by paper_2604_07170_amd.autotune) --
-    SPREAD_TILES = {1: (8, 8), 2: (16, 8), 3: (16, 16), 4: (32, 16), 5: (32, 32)}
+    SPREAD_TILES = {1: (8, 8), 2: (16, 8), 3: (16, 16), 4: (32, 16), 5: (32, 32), 6: (16, 16, "mfma")}
 
     def set_spread_tile(self, code: int):
         self._check(self.lib.wfp2d_set_spread_tile(self.h, int(code)))

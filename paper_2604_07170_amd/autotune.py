@@ -52,10 +52,12 @@ def _store(path, data):
 
 
 def tune_spread(plan, reps: int = 10, cache: str | None = None, retune: bool = False,
-                codes=(1, 2, 3, 4, 5)) -> dict:
+                codes=None) -> dict:
     """Select the fastest spreading tile shape for `plan` (cached per size class).
 
-    Returns {"class", "code", "tile", "ms": {code: ms} or None when cached}."""
+    Returns {"class", "code", "tile", "ms": {code: ms} or None when cached}.  `codes`
+    defaults to every shape the plan offers."""
+    codes = tuple(sorted(plan.SPREAD_TILES)) if codes is None else tuple(codes)
     path = cache_path() if cache is None else cache
     info = plan.info()
     key = size_class(info)

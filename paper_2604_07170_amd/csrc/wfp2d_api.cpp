@@ -143,11 +143,12 @@ static void *upload_real(Plan &p, const std::vector<double> &v)
     return d;
 }
 
-// Spreading tile shapes: code -> tile edge in x and y (fine-grid points).
+// Spreading tile shapes: code -> tile edge in x and y (fine-grid points); code 6 is the
+// 16 x 16 tile summed as a contraction on the matrix cores.
 static bool spread_tile_shape(int code, int &tx, int &ty)
 {
-    static const int shapes[6][2] = {{0, 0}, {8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
-    if (code < 1 || code > 5) return false;
+    static const int shapes[7][2] = {{0, 0}, {8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}, {16, 16}};
+    if (code < 1 || code > 6) return false;
     tx = shapes[code][0];
     ty = shapes[code][1];
     return true;
@@ -158,7 +159,7 @@ static bool spread_tile_shape(int code, int &tx, int &ty)
 static void build_spread_tiles(Plan &p, int code)
 {
     int tx, ty;
-    if (!spread_tile_shape(code, tx, ty)) fail(WFP2D_ERR_ARG, "spread tile code must be in [1, 5]");
+    if (!spread_tile_shape(code, tx, ty)) fail(WFP2D_ERR_ARG, "spread tile code must be in [1, 6]");
     const Geom &g = p.g;
     const int w = g.w;
     const int ntx = (g.Lpad + tx - 1) / tx, nty = (g.Lpad + ty - 1) / ty;
@@ -961,7 +962,7 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
         if (opts) o = *opts;
         if (o.precision != WFP2D_PREC_FP64 && o.precision != WFP2D_PREC_MIXED) fail(WFP2D_ERR_ARG, "unknown precision");
         if (o.interp_order < 2 || o.interp_order > 32) fail(WFP2D_ERR_ARG, "interp_order must be in [2, 32]");
-        if (o.spread_tile < 0 || o.spread_tile > 5) fail(WFP2D_ERR_ARG, "spread_tile must be in [0, 5]");
+        if (o.spread_tile < 0 || o.spread_tile > 6) fail(WFP2D_ERR_ARG, "spread_tile must be in [0, 6]");
         if (o.local_pairs != 0 && o.local_pairs != -1) fail(WFP2D_ERR_ARG, "local_pairs must be 0 (auto) or -1 (never)");
         if ((o.host_pointers != 0 && o.host_pointers != 1) || (o.check_finite != 0 && o.check_finite != 1))
             fail(WFP2D_ERR_ARG, "host_pointers and check_finite must be 0 or 1");
@@ -995,7 +996,7 @@ wfp2d_status wfp2d_init(wfp2d_plan *out, int64_t M, const double *src_xy, int64_
         p.nufft_tol = o.nufft_tol;
         p.device = o.device;
         p.stream = (hipStream_t)o.stream;
-        p.spread_tile = o.spread_tile ? o.spread_tile : 3;
+        p.spread_tile = o.spread_tile ? o.spread_tile : 6;
         p.opts = o;
         p.h_src_xy.assign(src_xy, src_xy + 2 * M);
         p.h_tgt_xy.assign(tgt_xy, tgt_xy + 2 * Nx);

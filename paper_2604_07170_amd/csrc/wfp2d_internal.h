@@ -177,7 +177,7 @@ struct Plan {
     void *d_src_wts = nullptr;        // [M][2w] Real
     int32_t *d_tile_off = nullptr, *d_tile_src = nullptr;
     std::vector<int2> h_src_base;     // host copy, to rebuild the tile lists for another tile shape
-    int32_t spread_tile = 3;          // tile shape code (see wfp2d_set_spread_tile)
+    int32_t spread_tile = 6;          // tile shape code (see wfp2d_set_spread_tile)
     int32_t sp_tx = 32, sp_ty = 32, sp_ntx = 1, sp_nty = 1;
     void *d_grid = nullptr;           // [Lpad][Lpad] complex Real
     void *d_T1 = nullptr;             // [Lpad][N] complex Real (rows transformed)

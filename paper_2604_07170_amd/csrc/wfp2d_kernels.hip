@@ -162,6 +162,115 @@ __global__ __launch_bounds__(64) void k_spread(const double *__restrict__ sig, c
 }
 
 // ---------------------------------------------------------------------------
+// The same type-1 input sums on the matrix cores.  The kernel is a tensor
+// product, so on a 16 x 16 tile the sum over the tile's sources is a
+// contraction over them:
+//   G[y][x] = sum_k (c_k wy_k(y - by_k)) wx_k(x - bx_k) = (A B)[y][x],
+// A[y][k] = c_k wy_k(y - by_k) and B[k][x] = wx_k(x - bx_k), both zero off the
+// kernel's support.  Every four staged sources take one 16x16x4 MFMA per part
+// (real part: c = S(t_m) samples, imaginary part: S(t_{m-LA})), in a fixed
+// order, so the sums are deterministic.  Operand layout of the 16x16x4 MFMAs:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it receives
+// D[4 (l / 16) + v][l % 16] (FP32) or D[l / 16 + 4 v][l % 16] (FP64), v < 4.
+// The sources' weights are staged cooperatively with 16-byte loads (each
+// source's 2w weights are one contiguous row).
+// ---------------------------------------------------------------------------
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <class R> struct mfma_acc;
+template <> struct mfma_acc<float> {
+    using T = mfma_f4;
+    static __device__ __forceinline__ T step(float a, float b, T c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct mfma_acc<double> {
+    using T = mfma_d4;
+    static __device__ __forceinline__ T step(double a, double b, T c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <class R>
+__global__ __launch_bounds__(64) void k_spread_mfma(const double *__restrict__ sig, const int64_t *__restrict__ step,
+                                                    const int2 *__restrict__ base, const R *__restrict__ wts,
+                                                    const int32_t *__restrict__ tile_off, const int32_t *__restrict__ tile_src,
+                                                    typename cplx<R>::T *__restrict__ grid, int w, int ntx, int ntile,
+                                                    int Lpad, Geom g)
+{
+    using C = typename cplx<R>::T;
+    using M = mfma_acc<R>;
+    extern __shared__ unsigned char spread_lds[];
+    __shared__ R st_c[64][2];
+    __shared__ int2 st_b[64];
+    __shared__ int st_j[64];
+    const int ws = 2 * w + 1;                      // staged weights per source (odd stride: no bank aliasing)
+    R *st_w = (R *)spread_lds;                     // [64][ws]
+    const int per_xcd = (ntile + 7) >> 3;
+    const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= ntile) return;
+    const int64_t m = step[0] - g.lookahead;
+    const double *__restrict__ sig_cur = sig + pmod(m, g.sig_depth) * g.M;
+    const double *__restrict__ sig_lag = sig + pmod(m - g.LA, g.sig_depth) * g.M;
+    const int ox = (tile % ntx) * 16, oy = (tile / ntx) * 16;
+    const int lane = threadIdx.x, q = lane & 15, kq = lane >> 4;
+    typename M::T are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+    constexpr int PER = 16 / (int)sizeof(R);       // weights per 16-byte load
+    const bool vec = (2 * w) % PER == 0;
+    const int nv = vec ? 2 * w / PER : 0;          // 16-byte loads per source
+    const int beg = tile_off[tile], end = tile_off[tile + 1];
+    for (int r0 = beg; r0 < end; r0 += 64) {
+        const int ns = min(64, end - r0);
+        if (lane < ns) {
+            const int j = tile_src[r0 + lane];
+            st_j[lane] = j;
+            st_c[lane][0] = (R)sig_cur[j];
+            st_c[lane][1] = (R)sig_lag[j];
+            const int2 b = base[j];
+            st_b[lane] = make_int2(b.x - ox, b.y - oy);
+            if (!vec)
+                for (int a = 0; a < 2 * w; ++a) st_w[lane * ws + a] = wts[(size_t)j * 2 * w + a];
+        }
+        if (vec) {
+            __syncthreads();
+            for (int i = lane; i < ns * nv; i += 64) {
+                const int s = i / nv, a = i - s * nv;
+                const float4 v4 = reinterpret_cast<const float4 *>(wts + (size_t)st_j[s] * 2 * w)[a];
+                const R *vr = reinterpret_cast<const R *>(&v4);
+#pragma unroll
+                for (int k = 0; k < PER; ++k) st_w[s * ws + a * PER + k] = vr[k];
+            }
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < ns; k0 += 4) {
+            const int k = k0 + kq;
+            R ar = R(0), ai = R(0), bx = R(0);
+            if (k < ns) {
+                const int2 b = st_b[k];
+                const R *wk = st_w + k * ws;
+                const int dy = q - b.y, dx = q - b.x;
+                if ((unsigned)dy < (unsigned)w) {
+                    const R wy = wk[w + dy];
+                    ar = st_c[k][0] * wy;
+                    ai = st_c[k][1] * wy;
+                }
+                if ((unsigned)dx < (unsigned)w) bx = wk[dx];
+            }
+            are = M::step(ar, bx, are);
+            aim = M::step(ai, bx, aim);
+        }
+        __syncthreads();
+    }
+    const int gx = ox + q;
+    if (gx < Lpad) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int gy = oy + M::row(lane, v);
+            if (gy < Lpad) grid[(size_t)gy * Lpad + gx] = C{are[v], aim[v]};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Line FFTs of length Q = 2^L (L >= 4) in one workgroup of T = Q/16 threads.
 // Each thread holds 16 values; Stockham passes of radix 16 run in registers
 // with one LDS exchange per pass, and a last pass of radix 2, 4 or 8 covers
@@ -1101,7 +1210,6 @@ __device__ __forceinline__ int fast_panel(const LocalArgs &A, double r, int W, d
 // lanes reading different panels (and sources) spread over the LDS banks.
 constexpr int kPsiRow = kChebDeg + 1;
 constexpr int kFastRB = 4;       // 16-row blocks of the coefficient table per wave (rows <= 64 per wave)
-typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int psi_src_stride(int n_reg) { return n_reg * kPsiRow + 1; }
 
 template <int NL>
@@ -1979,6 +2087,21 @@ static hipError_t spread_as(Plan &p)
     return hipGetLastError();
 }
 
+// the contraction form on 16 x 16 tiles (the source lists of shape 16 x 16)
+template <class R>
+static hipError_t spread_mfma(Plan &p)
+{
+    const Geom &g = p.g;
+    if (p.sp_tx != 16 || p.sp_ty != 16 || g.w > 16) return hipErrorInvalidValue;
+    const size_t lds = (size_t)64 * (2 * g.w + 1) * sizeof(R);
+    const int ntile = p.sp_ntx * p.sp_nty;
+    const unsigned nblk = (unsigned)(((ntile + 7) >> 3) << 3);
+    hipLaunchKernelGGL((k_spread_mfma<R>), dim3(nblk), dim3(64), lds, p.stream, p.d_sig, p.d_step, p.d_src_base,
+                       (const R *)p.d_src_wts, p.d_tile_off, p.d_tile_src, (typename cplx<R>::T *)p.d_grid, g.w,
+                       p.sp_ntx, ntile, g.Lpad, g);
+    return hipGetLastError();
+}
+
 template <class R>
 static hipError_t spread_typed(Plan &p)
 {
@@ -1988,6 +2111,7 @@ static hipError_t spread_typed(Plan &p)
     case 3: return spread_as<R, 16, 16>(p);
     case 4: return spread_as<R, 32, 16>(p);
     case 5: return spread_as<R, 32, 32>(p);
+    case 6: return spread_mfma<R>(p);
     default: return hipErrorInvalidValue;
     }
 }

@@ -155,7 +155,7 @@ def test_spread_tile_shapes_agree(precision):
     dev = torch.device("cuda", 0)
     params = w.torch_params(dev)
     outs = {}
-    for code in (1, 2, 3, 4, 5):
+    for code in (1, 2, 3, 4, 5, 6):
         plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=precision, interp_order=w.p, spread_tile=code)
         assert plan.info()["spread_tile"] == code
         for n in range(1, 61):
@@ -183,7 +183,7 @@ def test_spread_is_deterministic_on_every_tile_shape(precision):
     rng = np.random.default_rng(5)
     samples = [torch.from_numpy(rng.standard_normal(w.M)).to(dev) for _ in range(12)]
     ref = None
-    for code in (1, 2, 3, 4, 5):
+    for code in (1, 2, 3, 4, 5, 6):
         got = []
         for _ in range(2):
             plan = pa.Wfp2d(w.src, w.tgt, w.dt, w.W, w.tol, precision=precision, interp_order=w.p, spread_tile=code)

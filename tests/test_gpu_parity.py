@@ -48,11 +48,15 @@ def test_config0_displaced_targets():
     assert err <= TOL_E2E
 
 
-def test_stage_type1_against_direct_sum(cfg0):
+@pytest.mark.parametrize("tile", [3, 6])
+def test_stage_type1_against_direct_sum(cfg0, tile):
+    """The type-1 sums against the direct Fourier sum over the sources, on the vector-unit
+    16 x 16 tiles (code 3) and on the matrix-core contraction (code 6)."""
     import paper_2604_07170_amd as pa
     w = cfg0
     for precision, tol in [("fp64", 1e-10), ("mixed", 3e-6)]:
-        plan, _ = run_plan(w, precision, nsteps=60, record=set())
+        plan, _ = run_plan(w, precision, nsteps=60, record=set(), spread_tile=tile)
+        assert plan.info()["spread_tile"] == tile
         info = plan.info()
         m = info["step_reported"]
         modes = plan.debug(pa.STAGE.MODES).astype(np.float64)
