@@ -825,7 +825,10 @@ __global__ __launch_bounds__(256) void k_far(const int32_t *__restrict__ far_pk,
 // One workgroup per kTile x kTile tile of stencil origins: it stages the tile
 // and its w - 1 halo rows and columns of the grid in LDS with coalesced row
 // loads (each grid value is read from memory about (1 + (w - 1)/kTile)^2 times
-// in all), then each thread evaluates whole targets of the tile from LDS.
+// in all), then each thread evaluates whole targets of the tile from LDS.  With an
+// FP32 grid every staging load of a thread is issued before its first LDS store, and
+// its first target's data is loaded before the staging (one memory latency per
+// workgroup instead of one per staging round).
 // Tiles are remapped so that each XCD (workgroups are dealt to the 8 XCDs in
 // turn) takes one contiguous band of tiles, whose halos then meet in its L2.
 // Accumulation in FP64.
@@ -845,20 +848,73 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const R *__restrict__
     const int e0 = toff[tile], e1 = toff[tile + 1];
     if (e0 == e1) return;
     const int ox = (tile % ntx) * kTile, oy = (tile / ntx) * kTile, S = kTile + w - 1, ld = S + 1;
-    for (int q = threadIdx.x; q < S * S; q += kInterpThreads) {
-        const int yy = q / S, xx = q - yy * S, gx = ox + xx, gy = oy + yy;
-        tl[yy * ld + xx] = (gx < Lpad && gy < Lpad) ? cgrid[(size_t)gy * Lpad + gx] : R(0);
+    if constexpr (sizeof(R) == 8) {
+        // FP64 grid: the tile staged by a plain loop, targets read after it (measured faster in
+        // FP64 than the prefetching form below, whose registers lower the occupancy)
+        for (int q = threadIdx.x; q < S * S; q += kInterpThreads) {
+            const int yy = q / S, xx = q - yy * S, gx = ox + xx, gy = oy + yy;
+            tl[yy * ld + xx] = (gx < Lpad && gy < Lpad) ? cgrid[(size_t)gy * Lpad + gx] : R(0);
+        }
+        __syncthreads();
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += kInterpThreads) {
+            const int2 b = base[e];
+            const R *__restrict__ wi = wts + (size_t)e * 2 * w;
+            double wx[WM], wy[WM];
+#pragma unroll
+            for (int a = 0; a < WM; ++a) {
+                wx[a] = a < w ? (double)wi[a] : 0.0;
+                wy[a] = a < w ? (double)wi[w + a] : 0.0;
+            }
+            const R *row = tl + (b.y - oy) * ld + (b.x - ox);
+            double acc = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < WM; ++bb) {
+                if (bb < w) {
+                    double sx = 0.0;
+#pragma unroll
+                    for (int a = 0; a < WM; ++a)
+                        if (a < w) sx = fma(wx[a], (double)row[bb * ld + a], sx);
+                    acc = fma(sx, wy[bb], acc);
+                }
+            }
+            uh[tlist[e]] = acc;
+        }
+        return;
     }
-    __syncthreads();
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += kInterpThreads) {
-        const int2 b = base[e];                       // origins and weights are stored in processing order
+    // FP32 grid: this thread's first target (origin, weights, output slot) is loaded before the
+    // tile, so that its latency overlaps the staging
+    int2 b = make_int2(ox, oy);
+    int dst = 0;
+    R wr[2 * WM];
+    auto load_target = [&](int e) {
+        b = base[e];                                  // origins and weights are stored in processing order
+        dst = tlist[e];
         const R *__restrict__ wi = wts + (size_t)e * 2 * w;
-        double wx[WM], wy[WM];
 #pragma unroll
         for (int a = 0; a < WM; ++a) {
-            wx[a] = a < w ? (double)wi[a] : 0.0;
-            wy[a] = a < w ? (double)wi[w + a] : 0.0;
+            wr[a] = a < w ? wi[a] : R(0);
+            wr[WM + a] = a < w ? wi[w + a] : R(0);
         }
+    };
+    int e = e0 + (int)threadIdx.x;
+    if (e < e1) load_target(e);
+    // the tile and its halo: every load issued before the first LDS store (fixed count)
+    constexpr int SMAX = kTile + WM - 1, NIT = (SMAX * SMAX + kInterpThreads - 1) / kInterpThreads;
+    R tv[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int q = (int)threadIdx.x + i * kInterpThreads;
+        const int yy = q / S, xx = q - yy * S, gx = ox + xx, gy = oy + yy;
+        tv[i] = (q < S * S && gx < Lpad && gy < Lpad) ? cgrid[(size_t)gy * Lpad + gx] : R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int q = (int)threadIdx.x + i * kInterpThreads;
+        const int yy = q / S, xx = q - yy * S;
+        if (q < S * S) tl[yy * ld + xx] = tv[i];
+    }
+    __syncthreads();
+    for (; e < e1; e += kInterpThreads) {
         const R *row = tl + (b.y - oy) * ld + (b.x - ox);
         double acc = 0.0;
 #pragma unroll
@@ -867,11 +923,12 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const R *__restrict__
                 double sx = 0.0;
 #pragma unroll
                 for (int a = 0; a < WM; ++a)
-                    if (a < w) sx = fma(wx[a], (double)row[bb * ld + a], sx);
-                acc = fma(sx, wy[bb], acc);
+                    if (a < w) sx = fma((double)wr[a], (double)row[bb * ld + a], sx);
+                acc = fma(sx, (double)wr[WM + bb], acc);
             }
         }
-        uh[tlist[e]] = acc;
+        uh[dst] = acc;
+        if (e + kInterpThreads < e1) load_target(e + kInterpThreads);
     }
 }
 
