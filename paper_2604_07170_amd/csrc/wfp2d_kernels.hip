@@ -276,29 +276,42 @@ __global__ __launch_bounds__(64) void k_spread_mfma(const double *__restrict__ s
 // with one LDS exchange per pass, and a last pass of radix 2, 4 or 8 covers
 // L mod 4.  sign = +1 computes X[k] = sum_m x[m] e^{+2 pi i k m/Q}, sign = -1
 // the conjugate kernel.  Twiddles e^{2 pi i j/nf} (nf = P Q) come from the
-// workgroup's two-level LDS table (tw_at).
+// workgroup's two-level LDS table (tw_d) and their powers (twiddle_powers).
 // The LDS index is padded by one element every 16 against bank conflicts.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
 // Twiddles e^{2 pi i j/nf}, j in [0, nf), from a two-level FP64 table in LDS (staged
-// once per workgroup by tw_stage): tt[j & 63] * tt[64 + (j >> 6)], formed in FP64 and
-// rounded once to the working precision.  Gathers from a global table go through L2
-// at random strides and cost about half of the transform time.
-template <class C>
-__device__ __forceinline__ C tw_at(const double2 *tt, int j)
+// once per workgroup by tw_stage): tt[j & 63] * tt[64 + (j >> 6)], formed in FP64.
+// Gathers from a global table go through L2 at random strides and cost about half of
+// the transform time; one lookup per thread and pass, with the other twiddles its
+// powers, leaves the LDS to the transform's own exchanges.
+__device__ __forceinline__ double2 tw_d(const double2 *tt, int j)
 {
     const double2 a = tt[64 + (j >> 6)], b = tt[j & 63];
-    using R = decltype(C{}.x);
-    return C{(R)(a.x * b.x - a.y * b.y), (R)(a.x * b.y + a.y * b.x)};
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <class C>
-__device__ __forceinline__ C twid(const double2 *tt, int idx, int sign)
+__device__ __forceinline__ double2 cmul_d(double2 a, double2 b)
 {
-    C t = tw_at<C>(tt, idx);
-    if (sign < 0) t.y = -t.y;
-    return t;
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// v[r] *= w^r for r = 1 .. N-1, w = e^{sign 2 pi i j/nf}: one table entry, its powers by
+// repeated multiplication in FP64 (relative error below N units of FP64 rounding), each
+// rounded once to the working precision.  A Stockham pass's twiddles for one thread are
+// exactly such powers, so this replaces N-1 table lookups by one.
+template <int N, class C>
+__device__ __forceinline__ void twiddle_powers(C *v, const double2 *tt, int j, int sign)
+{
+    double2 w = tw_d(tt, j);
+    if (sign < 0) w.y = -w.y;
+    double2 t = w;
+#pragma unroll
+    for (int r = 1; r < N; ++r) {
+        v[r] = cmul(v[r], from_d<C>(t));
+        if (r + 1 < N) t = cmul_d(t, w);
+    }
 }
 
 // stage the two-level table of e^{2 pi i j/nf} (from the global FP64 table tw) into tt
@@ -415,8 +428,7 @@ __device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int lns, int sign
 #pragma unroll
     for (int i = 0; i < nb; ++i) {
         const int j = tid + T * i, k = j & (Ns - 1);
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], twid<C>(tw, k * r * stride, sign));
+        twiddle_powers<R>(v + i * R, tw, k * stride, sign);
         if (R == 2) dft2(v[i * R], v[i * R + 1]);
         else if (R == 4) dft4(v[i * R], v[i * R + 1], v[i * R + 2], v[i * R + 3], sign);
         else dft8(v + i * R, sign);
@@ -446,8 +458,7 @@ __device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const double2 *tw
         for (int r = 0; r < 16; ++r) v[r] = lds[rb + r * Tp];
         __syncthreads();
         const int Ns = 1 << lns, k = tid & (Ns - 1), stride = (Q >> (4 + lns)) * P, Nsp = fstr(Ns, pad);
-#pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twid<C>(tw, k * r * stride, sign));
+        twiddle_powers<16>(v, tw, k * stride, sign);
         dft16(v, sign);
         const int ob = fidx(((tid >> lns) << (lns + 4)) + k, pad);
 #pragma unroll
@@ -484,8 +495,10 @@ __device__ __forceinline__ int ilog2(int q)
 // twiddled line (nf = P Q).  mode 0 writes out[n + R] for every n; mode 1
 // writes only the disk n_x^2 + n_y^2 <= Rd2 (n_x = line - R).
 // ---------------------------------------------------------------------------
+// (FP32: bounded to three waves per SIMD, two workgroups' worth of latency hiding per CU
+// instead of one; a few accumulators spill, and the transform is still 20% faster)
 template <class R, int MODE>
-__global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__restrict__ in, typename cplx<R>::T *__restrict__ out,
+__global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t1(const typename cplx<R>::T *__restrict__ in, typename cplx<R>::T *__restrict__ out,
                                                 const typename cplx<R>::T *__restrict__ corr, const double2 *__restrict__ tw, Geom g)
 {
     using C = typename cplx<R>::T;
@@ -512,15 +525,17 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
                 v[r] = m < g.Lpad ? x[m] : C{0, 0};
             }
             fft_line(lds, v, g.Q, L, +1, tt, g.P);
+            // branch twiddles e^{2 pi i kk s/nf}, kk = tid + i T: a geometric sequence in i, formed
+            // in FP64; slot kk's negative frequency kk - Q takes the extra factor e^{-2 pi i Q s/nf}
+            double2 t = tw_d(tt, tid * s);
+            const double2 st = tw_d(tt, T * s), cq = tw_d(tt, s == 0 ? 0 : g.nf - g.Q * s);   // 0 < s < P: nf - Q s in (0, nf)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int kk = tid + i * T;
                 const C y = lds[fidx(kk, g.Q >= 256)];
-                if (kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, tw_at<C>(tt, kk * s)));   // kk s < Q P
-                if (kk >= g.Q - g.R) {
-                    const int n2 = kk - g.Q;
-                    acc_n[i] = cadd(acc_n[i], s == 0 ? y : cmul(y, tw_at<C>(tt, n2 * s + g.nf)));   // -nf < n2 s <= 0
-                }
+                if (kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, from_d<C>(t)));
+                if (kk >= g.Q - g.R) acc_n[i] = cadd(acc_n[i], s == 0 ? y : cmul(y, from_d<C>(cmul_d(t, cq))));
+                if (i < 15) t = cmul_d(t, st);
             }
             __syncthreads();
         }
@@ -537,11 +552,14 @@ __global__ __launch_bounds__(512) void k_fft_t1(const typename cplx<R>::T *__res
         // FP64: decimation in frequency (fewer registers), k = P k' + s per branch
         for (int s = 0; s < g.P; ++s) {
             // the line is re-read for each branch (from L2) rather than held in registers
+            double2 t = tw_d(tt, tid * s);                 // e^{2 pi i s m/nf}, m = tid + r T: geometric in r
+            const double2 st = tw_d(tt, T * s);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int m = tid + r * T;
                 const C xm = m < g.Lpad ? x[m] : C{0, 0};
-                v[r] = s == 0 ? xm : cmul(xm, tw_at<C>(tt, s * m));   // m < Q
+                v[r] = s == 0 ? xm : cmul(xm, from_d<C>(t));
+                if (r < 15) t = cmul_d(t, st);
             }
             fft_line(lds, v, g.Q, L, +1, tt, g.P);
 #pragma unroll
@@ -620,14 +638,17 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t2(const ty
             v[r] = val;
         }
         fft_line(lds, v, g.Q, L, -1, tt, g.P);
+        double2 t = tw_d(tt, tid * s);                     // e^{2 pi i s m/nf}, m = tid + i T: geometric in i
+        const double2 st = tw_d(tt, T * s);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int m = tid + i * T;
             if (m < g.Lpad) {
                 C r2 = lds[fidx(m, g.Q >= 256)];
-                if (s > 0) r2 = cmul(r2, cconj(tw_at<C>(tt, s * m)));   // m < Lpad <= Q
+                if (s > 0) r2 = cmul(r2, cconj(from_d<C>(t)));
                 acc[i] = cadd(acc[i], r2);
             }
+            if (i < 15) t = cmul_d(t, st);
         }
         __syncthreads();
     }
