@@ -395,6 +395,8 @@ static void build(Plan &p, const double *src_xy, const double *tgt_xy)
         }
     }
     if (best_nf < 0) fail(WFP2D_ERR_INFEASIBLE, "Fourier grid too large for the single-workgroup FFT");
+    // Q >= 2N/P by construction; the FP32 type-1 transform's slot layout relies on it
+    if (2 * (int64_t)N > (int64_t)g.P * g.Q) fail(WFP2D_ERR_INFEASIBLE, "Fourier grid shorter than the kept modes");
     g.w = w;
     g.ntx = g.Lpad / kTile;
 

@@ -515,9 +515,12 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t1(const ty
         // X(k) = sum_s e^{2 pi i k s/nf} FFT_Q(x_s)[k mod Q].  Slot k'' = k mod Q serves
         // n = k'' (if k'' <= R) and n = k'' - Q (if k'' >= Q - R); each thread accumulates
         // its slots over the branches and writes every output once, in natural order.
-        C acc_p[16], acc_n[16];
+        // The grid keeps 2R + 1 <= P Q / 2 <= 3 Q / 2 modes (checked at plan creation), so
+        // R < 12 T: slots i >= 12 (kk >= 12 T) never hold a nonnegative mode and slots i < 4
+        // (kk < 4 T < Q - R) never a negative one.  acc_p[i] serves i < 12, acc_n[i - 4] i >= 4.
+        C acc_p[12], acc_n[12];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc_p[i] = acc_n[i] = C{0, 0};
+        for (int i = 0; i < 12; ++i) acc_p[i] = acc_n[i] = C{0, 0};
         for (int s = 0; s < g.P; ++s) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -533,8 +536,9 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t1(const ty
             for (int i = 0; i < 16; ++i) {
                 const int kk = tid + i * T;
                 const C y = lds[fidx(kk, g.Q >= 256)];
-                if (kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, from_d<C>(t)));
-                if (kk >= g.Q - g.R) acc_n[i] = cadd(acc_n[i], s == 0 ? y : cmul(y, from_d<C>(cmul_d(t, cq))));
+                if (i < 12 && kk <= g.R) acc_p[i] = cadd(acc_p[i], s == 0 ? y : cmul(y, from_d<C>(t)));
+                if (i >= 4 && kk >= g.Q - g.R)
+                    acc_n[i - 4] = cadd(acc_n[i - 4], s == 0 ? y : cmul(y, from_d<C>(cmul_d(t, cq))));
                 if (i < 15) t = cmul_d(t, st);
             }
             __syncthreads();
@@ -542,11 +546,11 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t1(const ty
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int kk = tid + i * T;
-            if (kk <= g.R && !(MODE == 1 && (double)(nx * nx + kk * kk) > g.Rd2))
+            if (i < 12 && kk <= g.R && !(MODE == 1 && (double)(nx * nx + kk * kk) > g.Rd2))
                 out[(size_t)line * g.N + kk + g.R] = cmul(acc_p[i], corr[kk + g.R]);
             const int n2 = kk - g.Q;
-            if (kk >= g.Q - g.R && !(MODE == 1 && (double)(nx * nx + n2 * n2) > g.Rd2))
-                out[(size_t)line * g.N + n2 + g.R] = cmul(acc_n[i], corr[n2 + g.R]);
+            if (i >= 4 && kk >= g.Q - g.R && !(MODE == 1 && (double)(nx * nx + n2 * n2) > g.Rd2))
+                out[(size_t)line * g.N + n2 + g.R] = cmul(acc_n[i - 4], corr[n2 + g.R]);
         }
     } else {
         // FP64: decimation in frequency (fewer registers), k = P k' + s per branch
