@@ -378,11 +378,43 @@ template <class C> __device__ __forceinline__ void dft8(C *v, int sign)
     v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
 }
 
-template <class C> __device__ __forceinline__ void dft16(C *v, int sign)
+// dft4 of (a, b, c, d) whose inputs from the NB-th on are zero
+template <int NB, class C> __device__ __forceinline__ void dft4_z(C &a, C &b, C &c, C &d, int sign)
+{
+    if constexpr (NB >= 4) {
+        dft4(a, b, c, d, sign);
+    } else if constexpr (NB == 3) {                 // d = 0
+        const C s02 = cadd(a, c), d02 = csub(a, c), d13 = mul_si(b, sign);
+        a = cadd(s02, b);
+        c = csub(s02, b);
+        b = cadd(d02, d13);
+        d = csub(d02, d13);
+    } else if constexpr (NB == 2) {                 // c = d = 0
+        const C t = a, d13 = mul_si(b, sign);
+        a = cadd(t, b);
+        c = csub(t, b);
+        b = cadd(t, d13);
+        d = csub(t, d13);
+    } else if constexpr (NB == 1) {                 // b = c = d = 0
+        b = a;
+        c = a;
+        d = a;
+    } else {
+        a = b = c = d = C{0, 0};
+    }
+}
+
+// nonzero inputs among v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12] when v[r] = 0 for r >= NZ
+constexpr int dft16_nb(int nz, int n2) { return nz <= n2 ? 0 : ((nz - n2 + 3) / 4 > 4 ? 4 : (nz - n2 + 3) / 4); }
+
+// DFT of 16 values in registers; v[r] for r >= NZ must be zero (a pruned first stage)
+template <int NZ = 16, class C> __device__ __forceinline__ void dft16(C *v, int sign)
 {
     // n = 4 n1 + n2, k = k1 + 4 k2
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2], sign);
+    dft4_z<dft16_nb(NZ, 0)>(v[0], v[4], v[8], v[12], sign);
+    dft4_z<dft16_nb(NZ, 1)>(v[1], v[5], v[9], v[13], sign);
+    dft4_z<dft16_nb(NZ, 2)>(v[2], v[6], v[10], v[14], sign);
+    dft4_z<dft16_nb(NZ, 3)>(v[3], v[7], v[11], v[15], sign);
     // now v[4 k1 + n2] = Y[n2][k1]; twiddle by w16^{n2 k1}
 #pragma unroll
     for (int k1 = 1; k1 < 4; ++k1)
@@ -440,14 +472,14 @@ __device__ __forceinline__ void tail_pass(C *lds, C *v, int Q, int lns, int sign
 }
 
 // One workgroup transforms one line.  v[r] (r < 16) holds x[tid + r Q/16] on
-// entry; the result is left in lds (natural order, index fidx).
-template <class C>
+// entry, zero for r >= NZ; the result is left in lds (natural order, index fidx).
+template <int NZ = 16, class C>
 __device__ void fft_line(C *lds, C *v, int Q, int L, int sign, const double2 *tw, int P)
 {
     const bool pad = Q >= 256;
     const int tid = threadIdx.x, T = Q >> 4, Tp = fstr(T, pad), rb = fidx(tid, pad);
     // first radix-16 pass (Ns = 1): no twiddles; idx(16 tid + r) = idx(16 tid) + r
-    dft16(v, sign);
+    dft16<NZ>(v, sign);
     const int b1 = pad ? tid * 17 : tid * 16;
 #pragma unroll
     for (int r = 0; r < 16; ++r) lds[b1 + r] = v[r];
@@ -496,8 +528,10 @@ __device__ __forceinline__ int ilog2(int q)
 // writes only the disk n_x^2 + n_y^2 <= Rd2 (n_x = line - R).
 // ---------------------------------------------------------------------------
 // (FP32: bounded to three waves per SIMD, two workgroups' worth of latency hiding per CU
-// instead of one; a few accumulators spill, and the transform is still 20% faster)
-template <class R, int MODE>
+// instead of one.)  NZ: in the FP32 form, a branch line x_s is zero from element NZ T on
+// (P NZ T >= Lpad), so each thread loads NZ of its 16 values and the first radix-16 pass
+// is pruned accordingly.
+template <class R, int MODE, int NZ = 16>
 __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t1(const typename cplx<R>::T *__restrict__ in, typename cplx<R>::T *__restrict__ out,
                                                 const typename cplx<R>::T *__restrict__ corr, const double2 *__restrict__ tw, Geom g)
 {
@@ -525,9 +559,9 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 3 : 1) void k_fft_t1(const ty
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int m = g.P * (tid + r * T) + s;
-                v[r] = m < g.Lpad ? x[m] : C{0, 0};
+                v[r] = (r < NZ && m < g.Lpad) ? x[m] : C{0, 0};
             }
-            fft_line(lds, v, g.Q, L, +1, tt, g.P);
+            fft_line<NZ>(lds, v, g.Q, L, +1, tt, g.P);
             // branch twiddles e^{2 pi i kk s/nf}, kk = tid + i T: a geometric sequence in i, formed
             // in FP64; slot kk's negative frequency kk - Q takes the extra factor e^{-2 pi i Q s/nf}
             double2 t = tw_d(tt, tid * s);
@@ -2236,6 +2270,12 @@ static hipError_t fft_attrs(size_t bytes)
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_fft_t1<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
     if ((e = hipFuncSetAttribute((const void *)k_fft_t1<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if constexpr (sizeof(R) == 4) {
+        const void *pruned[] = {(const void *)k_fft_t1<R, 0, 5>, (const void *)k_fft_t1<R, 1, 5>, (const void *)k_fft_t1<R, 0, 6>,
+                                (const void *)k_fft_t1<R, 1, 6>, (const void *)k_fft_t1<R, 0, 8>, (const void *)k_fft_t1<R, 1, 8>};
+        for (const void *k : pruned)
+            if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    }
     if ((e = hipFuncSetAttribute((const void *)k_fft_t2<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
     return hipFuncSetAttribute((const void *)k_fft_t2<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
@@ -2253,14 +2293,30 @@ static void transpose(const Plan &p, const void *in, void *out, int rows, int co
     hipLaunchKernelGGL(k_transpose<C>, grid, dim3(256), 0, p.stream, (const C *)in, (C *)out, rows, cols);
 }
 
+// FP32 type-1 line transforms with the first pass pruned to the NZ nonzero values per
+// thread: NZ >= ceil(Lpad / (P T)), rounded up to an instantiated count
+template <int MODE>
+static void launch_t1_f32(Plan &p, const void *in, void *out, unsigned nlines)
+{
+    const Geom &g = p.g;
+    const size_t sh = fft_lds_bytes(p);
+    const int T = g.Q / 16, nz = (g.Lpad + g.P * T - 1) / (g.P * T);
+    const float2 *x = (const float2 *)in, *corr = (const float2 *)p.d_corr;
+    float2 *y = (float2 *)out;
+    const double2 *tw = (const double2 *)p.d_tw;
+    if (nz <= 5) hipLaunchKernelGGL((k_fft_t1<float, MODE, 5>), dim3(nlines), dim3(T), sh, p.stream, x, y, corr, tw, g);
+    else if (nz <= 6) hipLaunchKernelGGL((k_fft_t1<float, MODE, 6>), dim3(nlines), dim3(T), sh, p.stream, x, y, corr, tw, g);
+    else if (nz <= 8) hipLaunchKernelGGL((k_fft_t1<float, MODE, 8>), dim3(nlines), dim3(T), sh, p.stream, x, y, corr, tw, g);
+    else hipLaunchKernelGGL((k_fft_t1<float, MODE, 16>), dim3(nlines), dim3(T), sh, p.stream, x, y, corr, tw, g);
+}
+
 hipError_t launch_fft_rows1(Plan &p)
 {
     const Geom &g = p.g;
     const size_t sh = fft_lds_bytes(p);
     const unsigned T = (unsigned)(g.Q / 16);
     if (p.precision == WFP2D_PREC_MIXED)
-        hipLaunchKernelGGL((k_fft_t1<float, 0>), dim3(g.Lpad), dim3(T), sh, p.stream, (const float2 *)p.d_grid, (float2 *)p.d_T1,
-                           (const float2 *)p.d_corr, (const double2 *)p.d_tw, g);
+        launch_t1_f32<0>(p, p.d_grid, p.d_T1, (unsigned)g.Lpad);
     else
         hipLaunchKernelGGL((k_fft_t1<double, 0>), dim3(g.Lpad), dim3(T), sh, p.stream, (const double2 *)p.d_grid, (double2 *)p.d_T1,
                            (const double2 *)p.d_corr, (const double2 *)p.d_tw, g);
@@ -2274,8 +2330,7 @@ hipError_t launch_fft_cols1(Plan &p)
     const unsigned T = (unsigned)(g.Q / 16);
     if (p.precision == WFP2D_PREC_MIXED) {
         transpose<float2>(p, p.d_T1, p.d_T1t, g.Lpad, g.N);
-        hipLaunchKernelGGL((k_fft_t1<float, 1>), dim3(g.N), dim3(T), sh, p.stream, (const float2 *)p.d_T1t, (float2 *)p.d_F,
-                           (const float2 *)p.d_corr, (const double2 *)p.d_tw, g);
+        launch_t1_f32<1>(p, p.d_T1t, p.d_F, (unsigned)g.N);
     } else {
         transpose<double2>(p, p.d_T1, p.d_T1t, g.Lpad, g.N);
         hipLaunchKernelGGL((k_fft_t1<double, 1>), dim3(g.N), dim3(T), sh, p.stream, (const double2 *)p.d_T1t, (double2 *)p.d_F,
