@@ -43,6 +43,7 @@ HARNESS = r"""
 #include <complex>
 #include <cstdio>
 #include <random>
+#include <vector>
 #define __device__
 #define __forceinline__ inline
 struct float2 { float x, y; };
