@@ -8,34 +8,16 @@ functions' source text from the kernels file, compiles it as plain C++ with g++ 
 them with the definition X[k] = sum_m x[m] e^{sign 2 pi i k m/n} and with e^{sign 2 pi i j r/nf}
 evaluated directly.  Nothing here runs on a GPU or calls the oracle.
 """
-import os
-import re
 import shutil
 import subprocess
 
 import pytest
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNELS = os.path.join(ROOT, "paper_2604_07170_amd", "csrc", "wfp2d_kernels.hip")
+from kernel_source import definition, kernels_source
 
 # device functions needed, by the name in their definition line
 NAMES = ["cmul", "cadd", "csub", "from_d", "mul_si", "dft2", "dft4", "rot16", "dft8", "dft4_z", "dft16_nb", "dft16",
          "tw_d", "cmul_d", "twiddle_powers"]
-
-
-def _definition(src: str, name: str) -> str:
-    """Source text of the definition of `name` (with its template line), up to its closing brace."""
-    m = re.search(r"^(template <[^\n]*>\s*\n)?[^\n]*\b" + re.escape(name) + r"(<[^>\n]*>)?\(", src, re.M)
-    assert m, name
-    start = m.start()
-    line_end = src.index("\n", m.end())
-    first = src[start:line_end]
-    if name == "from_d":                                   # declaration + two one-line specialisations
-        end = src.index("from_d<double2>", start)
-        return src[start:src.index("\n", end)]
-    if first.rstrip().endswith("}"):
-        return first
-    return src[start:src.index("\n}\n", start) + 2]
 
 
 HARNESS = r"""
@@ -134,8 +116,8 @@ def results(tmp_path_factory):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
-    src = open(KERNELS).read()
-    blocks = "\n".join(_definition(src, n) for n in NAMES)
+    src = kernels_source()
+    blocks = "\n".join(definition(src, n) for n in NAMES)
     d = tmp_path_factory.mktemp("fftblocks")
     cpp, exe = d / "blocks.cpp", d / "blocks"
     cpp.write_text(HARNESS.replace("@BLOCKS@", blocks))
