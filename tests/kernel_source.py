@@ -36,9 +36,9 @@ alignas(64) char smem[1 << 20];
 
 
 def definition(src: str, name: str) -> str:
-    """Definition of `name` (with a template line right above it) up to its closing brace at
-    column 0, or the one line it takes."""
-    m = re.search(r"^(template <[^\n]*>\s*\n)?(?!\s*//)[^\n]*\b" + re.escape(name) + r"(<[^>\n]*>)?\(", src, re.M)
+    """Definition of `name` (with the bare template header line right above it, if any) up to
+    its closing brace at column 0, or the one line it takes."""
+    m = re.search(r"^(template <[^\n(]*\n)?(?!\s*//)[^\n]*\b" + re.escape(name) + r"(<[^>\n]*>)?\(", src, re.M)
     assert m, name
     start = m.start()
     first = src[start:src.index("\n", m.end())]
