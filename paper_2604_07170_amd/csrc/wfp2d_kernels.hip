@@ -234,8 +234,8 @@ __global__ __launch_bounds__(64) void k_spread_mfma(const double *__restrict__ s
             __syncthreads();
             for (int i = lane; i < ns * nv; i += 64) {
                 const int s = i / nv, a = i - s * nv;
-                const float4 v4 = reinterpret_cast<const float4 *>(wts + (size_t)st_j[s] * 2 * w)[a];
-                const R *vr = reinterpret_cast<const R *>(&v4);
+                R vr[PER];                         // one 16-byte load (rows are 16-byte aligned), no type punning
+                __builtin_memcpy(vr, __builtin_assume_aligned(wts + (size_t)st_j[s] * 2 * w + a * PER, 16), 16);
 #pragma unroll
                 for (int k = 0; k < PER; ++k) st_w[s * ws + a * PER + k] = vr[k];
             }

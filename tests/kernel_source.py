@@ -61,3 +61,17 @@ def kernels_source() -> str:
 
 def internal_source() -> str:
     return open(INTERNAL).read()
+
+
+def host_shared(text: str) -> str:
+    """Workgroup-shared arrays as function statics (one workgroup runs at a time on the host);
+    dynamic shared arrays stay extern globals of the harness."""
+    text = text.replace("extern __shared__", "extern")
+    return text.replace("__shared__", "static")
+
+
+def between(src: str, start: str, end: str) -> str:
+    """Source text from the line holding `start` up to (not including) the line holding `end`."""
+    i = src.rindex("\n", 0, src.index(start)) + 1
+    j = src.rindex("\n", 0, src.index(end, i)) + 1
+    return src[i:j]
