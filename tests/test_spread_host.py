@@ -1,4 +1,4 @@
-"""The matrix-core spreading kernel's indexing, compiled for the host with emulated MFMAs (CPU).
+"""The spreading kernels, compiled for the host (the matrix-core one with emulated MFMAs) (CPU).
 
 `k_spread_mfma` sums, on each 16 x 16 tile of the fine grid, the tensor-product kernels of the
 tile's sources (eq. sighat's spreading) as a contraction over them.  Here it is built from the
@@ -12,8 +12,9 @@ builds them, for tiles with no source, several 64-source chunks (a last chunk no
 4), supports at the band's edges, FP32 and FP64, and weight rows staged by 16-byte loads (2w a
 multiple of 16 bytes) or one by one.  This checks the kernel's tiling, staging, chunk loop and
 stores against the layout; that the hardware has this layout is checked by the GPU parity tests
-(`test_stage_type1_against_direct_sum` on tile code 6).  Nothing here runs on a GPU or calls the
-oracle.
+(`test_stage_type1_against_direct_sum` on tile code 6).  The vector-unit kernel `k_spread` of tile
+codes 1..5 (8x8 to 32x32 tiles, each lane accumulating its own points) is checked the same way.
+Nothing here runs on a GPU or calls the oracle.
 """
 import shutil
 import subprocess
@@ -58,7 +59,7 @@ V host_mfma(E a, E b, V c)
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) host_mfma<mfma_d4, double, false>(a, b, c)
 @BLOCKS@
 
-template <class R>
+template <class R, int TX, int TY, bool MF>
 void check(int Lpad, int w, int M, unsigned seed)
 {
     using C = typename cplx<R>::T;
@@ -80,11 +81,11 @@ void check(int Lpad, int w, int M, unsigned seed)
         else base[j] = make_int2((int)(rng() % (hi / 2 + 1)), (int)(rng() % (hi / 2 + 1)));
     }
     // per-tile source lists, as the plan builds them: each tile the support meets
-    const int ntx = (Lpad + 15) / 16, ntile = ntx * ntx;
+    const int ntx = (Lpad + TX - 1) / TX, nty = (Lpad + TY - 1) / TY, ntile = ntx * nty;
     std::vector<std::vector<int32_t>> lists(ntile);
     for (int j = 0; j < M; ++j)
-        for (int y = base[j].y / 16; y <= (base[j].y + w - 1) / 16; ++y)
-            for (int x = base[j].x / 16; x <= (base[j].x + w - 1) / 16; ++x) lists[y * ntx + x].push_back(j);
+        for (int y = base[j].y / TY; y <= (base[j].y + w - 1) / TY; ++y)
+            for (int x = base[j].x / TX; x <= (base[j].x + w - 1) / TX; ++x) lists[y * ntx + x].push_back(j);
     std::vector<int32_t> off(ntile + 1, 0), src;
     size_t most = 0;
     for (int t = 0; t < ntile; ++t) {
@@ -103,8 +104,12 @@ void check(int Lpad, int w, int M, unsigned seed)
         for (int t = 0; t < 64; ++t)
             th.emplace_back([&, t] {
                 threadIdx.x = t;
-                k_spread_mfma<R>(sig.data(), &step, base.data(), wts.data(), off.data(), src.data(), grid.data(), w, ntx,
-                                 ntile, Lpad, g);
+                if constexpr (MF)
+                    k_spread_mfma<R>(sig.data(), &step, base.data(), wts.data(), off.data(), src.data(), grid.data(), w, ntx,
+                                     ntile, Lpad, g);
+                else
+                    k_spread<R, TX, TY>(sig.data(), &step, base.data(), wts.data(), off.data(), src.data(), grid.data(), w,
+                                        ntx, ntile, Lpad, g);
             });
         for (auto &x : th) x.join();
     }
@@ -127,15 +132,21 @@ void check(int Lpad, int w, int M, unsigned seed)
         err = std::fmax(err, (double)std::fabs(im[q] - grid[q].y));
         big = std::fmax(big, (double)std::fmax(std::fabs(re[q]), std::fabs(im[q])));
     }
-    printf("%s %d %zu %.3e %ld\n", sizeof(R) == 4 ? "f32" : "f64", w, most, err / big, unwritten);
+    printf("%s %d %zu %.3e %ld %s\n", sizeof(R) == 4 ? "f32" : "f64", w, most, err / big, unwritten, MF ? "mfma" : "vector");
 }
 
 int main()
 {
-    check<float>(64, 8, 400, 1);      // 16-byte staging (2w = 16 floats)
-    check<float>(64, 7, 400, 2);      // one-by-one staging
-    check<double>(64, 12, 300, 3);    // 16-byte staging (2w = 24 doubles)
-    check<double>(48, 5, 300, 4);     // one-by-one staging, band not a multiple of 32
+    check<float, 16, 16, true>(64, 8, 400, 1);      // 16-byte staging (2w = 16 floats)
+    check<float, 16, 16, true>(64, 7, 400, 2);      // one-by-one staging
+    check<double, 16, 16, true>(64, 12, 300, 3);    // 16-byte staging (2w = 24 doubles)
+    check<double, 16, 16, true>(48, 5, 300, 4);     // one-by-one staging, band not a multiple of 32
+    // the vector-unit tiles (codes 1..5)
+    check<float, 8, 8, false>(64, 8, 400, 5);
+    check<float, 16, 8, false>(64, 7, 400, 6);
+    check<double, 16, 16, false>(64, 12, 300, 7);
+    check<float, 32, 16, false>(64, 8, 400, 8);
+    check<double, 32, 32, false>(48, 5, 300, 9);
 }
 """
 
@@ -149,8 +160,8 @@ def results(tmp_path_factory):
     acc = between(src, "template <class R> struct mfma_acc;", "__global__ __launch_bounds__(64) void k_spread_mfma(")
     acc = acc.rstrip()
     acc = acc[:acc.rindex("\n")] if acc.endswith("template <class R>") else acc   # the kernel's own header
-    blocks = "\n".join([struct(internal_source(), "Geom"), definition(src, "pmod"), acc,
-                        host_shared(definition(src, "k_spread_mfma"))])
+    blocks = "\n".join([struct(internal_source(), "Geom"), definition(src, "pmod"), host_shared(definition(src, "k_spread")),
+                        acc, host_shared(definition(src, "k_spread_mfma"))])
     d = tmp_path_factory.mktemp("spreadmfma")
     cpp, exe = d / "spread.cpp", d / "spread"
     cpp.write_text(HOST_PRELUDE + DRIVER.replace("@BLOCKS@", blocks))
@@ -158,13 +169,14 @@ def results(tmp_path_factory):
                     "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=240).stdout
     rows = [line.split() for line in out.strip().splitlines()]
-    assert len(rows) == 4, out
-    return [{"prec": f[0], "w": int(f[1]), "most": int(f[2]), "err": float(f[3]), "unwritten": int(f[4])} for f in rows]
+    assert len(rows) == 9, out
+    return [{"prec": f[0], "w": int(f[1]), "most": int(f[2]), "err": float(f[3]), "unwritten": int(f[4]), "form": f[5]}
+            for f in rows]
 
 
 def test_spread_grid_matches_the_direct_sum(results):
     for r in results:
-        assert r["most"] > 128 and r["err"] < (1e-6 if r["prec"] == "f32" else 1e-14), r
+        assert r["most"] > 64 and r["err"] < (1e-6 if r["prec"] == "f32" else 1e-14), r
 
 
 def test_every_grid_point_written(results):
