@@ -26,7 +26,7 @@ struct float2 { float x, y; };
 struct double2 { double x, y; };
 inline float2 make_float2(float x, float y) { return float2{x, y}; }
 inline double2 make_double2(double x, double y) { return double2{x, y}; }
-struct HostDim { unsigned x; };
+struct HostDim { unsigned x, y; };
 thread_local HostDim threadIdx;
 HostDim blockIdx, blockDim;
 std::barrier<> *host_group = nullptr;
