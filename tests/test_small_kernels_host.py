@@ -7,6 +7,10 @@
 * `k_combine` returns u = u_h + u_l in caller order (target i from the plan's slot rank[i]), and 0
   while the reported step is not yet positive (zero initial data).
 * `k_transpose` writes out[c][r] = in[r][c] for sizes that are not multiples of its 32 x 32 tile.
+* `k_local_dyadic` adds, for each pair with r < dt/2 (Sec. 6, eq. ul_GL on the dyadic panels), its
+  weighted levels sum_d w_d(q) sigma_s(t_{m - lev_min - d}) to u_l at its target; checked with
+  several pairs per target, a grid smaller than the pair count (the grid-stride loop) and the
+  sigma ring wrapping.
 Each is built from the kernels file as plain C++ (host threads as lanes, a barrier for the
 transpose's __syncthreads).  Nothing here runs on a GPU or calls the oracle.
 """
@@ -15,7 +19,7 @@ import subprocess
 
 import pytest
 
-from kernel_source import HOST_PRELUDE, definition, host_shared, kernels_source
+from kernel_source import HOST_PRELUDE, definition, host_shared, internal_source, kernels_source, struct
 
 DRIVER = r"""
 #include <algorithm>
@@ -26,6 +30,8 @@ inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v)
 {
     return std::atomic_ref<unsigned long long>(*p).fetch_add(v);
 }
+inline double unsafeAtomicAdd(double *p, double v) { return std::atomic_ref<double>(*p).fetch_add(v); }
+HostDim gridDim;
 @BLOCKS@
 
 template <class F> void grid1d(int64_t n, F f)
@@ -115,6 +121,43 @@ int main()
             }
     }
     printf("transpose %ld\n", bad);
+    // dyadic local pairs
+    bad = 0;
+    {
+        Geom g{};
+        g.M = 50; g.lookahead = 9; g.lev_min = 2; g.nlev = 27; g.sig_depth = 31;
+        const int64_t ndy = 3000, Nt = 40, st = 100;
+        std::vector<double> sig((size_t)g.sig_depth * g.M), dw((size_t)g.nlev * ndy), ul(Nt, 0.0);
+        for (auto &v : sig) v = nd(rng);
+        for (auto &v : dw) v = nd(rng);
+        std::vector<int32_t> dtg(ndy), dsg(ndy);
+        for (int64_t q = 0; q < ndy; ++q) { dtg[q] = (int32_t)(rng() % Nt); dsg[q] = (int32_t)(rng() % g.M); }
+        std::sort(dtg.begin(), dtg.end());
+        LocalArgs A{};
+        A.sig = sig.data();
+        A.ul = ul.data();
+        PairLists P{};
+        P.dw = dw.data(); P.dtg = dtg.data(); P.dsg = dsg.data(); P.ndy = ndy;
+        gridDim.x = 4;
+        blockDim.x = 256;
+        for (unsigned b = 0; b < gridDim.x; ++b) {
+            blockIdx.x = b;
+            std::barrier<> bar(256);
+            host_group = &bar;
+            std::vector<std::thread> th;
+            for (int t = 0; t < 256; ++t) th.emplace_back([&, t] { threadIdx.x = t; k_local_dyadic(A, P, &st, g); });
+            for (auto &x : th) x.join();
+        }
+        std::vector<long double> ref(Nt, 0.0L);
+        const int64_t m = st - g.lookahead;
+        for (int64_t q = 0; q < ndy; ++q)
+            for (int d = 0; d < g.nlev; ++d) {
+                const int64_t lvl = m - g.lev_min - d, slot = ((lvl % g.sig_depth) + g.sig_depth) % g.sig_depth;
+                ref[dtg[q]] += (long double)dw[(size_t)d * ndy + q] * sig[(size_t)slot * g.M + dsg[q]];
+            }
+        for (int t = 0; t < Nt; ++t) bad += std::fabs((double)ref[t] - ul[t]) > 1e-12 * (1.0 + std::fabs((double)ref[t]));
+    }
+    printf("dyadic %ld\n", bad);
 }
 """
 
@@ -125,8 +168,12 @@ def results(tmp_path_factory):
     if gxx is None:
         pytest.skip("g++ not available")
     src = kernels_source()
+    inl = internal_source()
+    consts = "\n".join(l for l in inl.splitlines() if l.startswith("constexpr int kLocalMaxLevels"))
     blocks = "\n".join([definition(src, "pmod"), definition(src, "k_ingest"), definition(src, "k_ingest_slot"),
-                        definition(src, "k_combine"), host_shared(definition(src, "k_transpose"))])
+                        definition(src, "k_combine"), host_shared(definition(src, "k_transpose")), consts,
+                        struct(inl, "Geom"), struct(inl, "SubPanel"), struct(src, "LocalArgs"), "struct LpDesc;",
+                        struct(src, "PairLists"), definition(src, "sig_slot"), host_shared(definition(src, "k_local_dyadic"))])
     d = tmp_path_factory.mktemp("small")
     cpp, exe = d / "small.cpp", d / "small"
     cpp.write_text(HOST_PRELUDE + DRIVER.replace("@BLOCKS@", blocks))
@@ -135,6 +182,6 @@ def results(tmp_path_factory):
     return {f[0]: int(f[1]) for f in (line.split() for line in out.strip().splitlines())}
 
 
-@pytest.mark.parametrize("kernel", ["ingest", "combine", "transpose"])
+@pytest.mark.parametrize("kernel", ["ingest", "combine", "transpose", "dyadic"])
 def test_small_kernel_matches_its_definition(results, kernel):
     assert results[kernel] == 0, results
